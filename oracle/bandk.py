@@ -1,0 +1,275 @@
+"""Oracle: Band-k reordering and CSR-k grouping ("BandK-v1") — TEST INFRASTRUCTURE ONLY.
+
+What the paper fixes (Section 2.2, the Band-k algorithm and Fig. 2): the
+matrix is turned into a graph; the graph is coarsened over k levels; every
+coarse level is reordered with a weighted bandwidth-limiting ordering; the
+coarse nodes are then expanded level by level, the vertices inside each coarse
+node being reordered with a bandwidth-limiting ordering; and the levels give the
+super-rows (SR) and super-super-rows (SSR).  The paper leaves the coarsening
+rule, the ordering algorithm, its tie-breaks, the start vertex and the
+treatment of nonsymmetric patterns unstated.  This module takes one fixed,
+deterministic reading of those gaps (listed in the project design notes):
+
+1.  G0: vertex per row; undirected edge {i, j}, i != j, whenever (i, j) or
+    (j, i) is stored; edge weight 1; deg = number of distinct neighbours.
+2.  CM(G): repeated FIFO breadth-first search.  A new search starts at the
+    unvisited vertex with the smallest (deg, id).  When a vertex is taken from
+    the queue it is appended to the sequence and its unvisited neighbours are
+    queued in the order of the key (-w(u, v), deg(v), id(v)).  RCM = CM reversed.
+3.  Aggregate(G, t): cut CM(G) (not reversed) into consecutive chunks of t
+    vertices; only the last chunk may be shorter.  A coarse vertex's id is the
+    smallest original row number it contains.
+4.  Quotient: coarse edge {A, B} of weight sum of w(u, v) over fine edges with
+    u in A, v in B.
+5.  k = 3: G1 = Quotient(Aggregate(G0, SRS)), G2 = Quotient(Aggregate(G1, SSRS));
+    the SSRs are the vertices of G2 in RCM(G2) order.
+6.  Expand(G_low, order_up): for each upper vertex in order, emit its children
+    by LocalOrder: start at the not-yet-emitted child with the smallest
+    (-wp(v), deg(v), id(v)), wp(v) = sum of w(u, v) over vertices u of this level
+    already emitted; breadth-first search inside the child set with the
+    neighbour key of step 2; repeat until every child is emitted.
+    order1 = Expand(G1, order2) is the SR order; perm = Expand(G0, order1).
+7.  sr_ptr / ssr_ptr are running counts of rows per SR and SRs per SSR
+    (Section 2.2 and Fig. 1).
+
+The ordering's *quality* is parity unpinned: no implementation of the paper's
+Band-k exists to compare against; only this reading is pinned (worked example,
+special cases and invariants in tests/test_oracle_bandk.py).
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class LevelGraph:
+    """Undirected weighted graph; adjacency sorted by vertex index; ``ident`` = smallest original row."""
+
+    n: int
+    xadj: np.ndarray  # int64[n+1]
+    adj: np.ndarray   # int64[2|E|]
+    wgt: np.ndarray   # int64[2|E|]
+    ident: np.ndarray  # int64[n]
+
+    @property
+    def deg(self) -> np.ndarray:
+        return np.diff(self.xadj)
+
+
+def graph_from_csr(row_ptr, col_idx) -> LevelGraph:
+    """G0: symmetrised pattern without the diagonal; every edge weight is 1."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col_idx = np.asarray(col_idx, dtype=np.int64)
+    n = len(row_ptr) - 1
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    off = rows != col_idx
+    a = np.concatenate([rows[off], col_idx[off]])
+    b = np.concatenate([col_idx[off], rows[off]])
+    key = np.unique(a * max(n, 1) + b)
+    src = key // max(n, 1)
+    dst = key % max(n, 1)
+    xadj = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=xadj[1:])
+    return LevelGraph(n, xadj, dst, np.ones(len(dst), dtype=np.int64), np.arange(n, dtype=np.int64))
+
+
+def cuthill_mckee(G: LevelGraph) -> list:
+    """Weighted Cuthill-McKee sequence of all vertices (step 2 of the module notes)."""
+    n = G.n
+    xadj = G.xadj.tolist()
+    adj = G.adj.tolist()
+    wgt = G.wgt.tolist()
+    deg = G.deg.tolist()
+    ident = G.ident.tolist()
+    starts = sorted(range(n), key=lambda v: (deg[v], ident[v]))
+    visited = [False] * n
+    seq = []  # doubles as the FIFO queue: the dequeue order equals the enqueue order
+    for s in starts:
+        if visited[s]:
+            continue
+        visited[s] = True
+        head = len(seq)
+        seq.append(s)
+        while head < len(seq):
+            u = seq[head]
+            head += 1
+            cand = []
+            for p in range(xadj[u], xadj[u + 1]):
+                v = adj[p]
+                if not visited[v]:
+                    cand.append((-wgt[p], deg[v], ident[v], v))
+            cand.sort()
+            for c in cand:
+                visited[c[3]] = True
+                seq.append(c[3])
+    return seq
+
+
+def reverse_cuthill_mckee(G: LevelGraph) -> list:
+    return cuthill_mckee(G)[::-1]
+
+
+def aggregate(G: LevelGraph, t: int):
+    """Chunks of t consecutive vertices of CM(G); coarse vertices indexed by increasing id.
+
+    Returns ``(agg, children, ident)``: fine->coarse index, the fine vertices of
+    each coarse vertex, and each coarse vertex's id (smallest original row).
+    """
+    if t < 1:
+        raise ValueError("chunk size must be >= 1")
+    seq = cuthill_mckee(G)
+    chunks = [seq[i:i + t] for i in range(0, len(seq), t)]
+    cid = [min(int(G.ident[v]) for v in ch) for ch in chunks]
+    order = sorted(range(len(chunks)), key=lambda c: cid[c])
+    children = [sorted(chunks[c]) for c in order]
+    ident = np.array([cid[c] for c in order], dtype=np.int64)
+    agg = np.empty(G.n, dtype=np.int64)
+    for c, ch in enumerate(children):
+        agg[ch] = c
+    return agg, children, ident
+
+
+def quotient(G: LevelGraph, agg: np.ndarray, ident: np.ndarray) -> LevelGraph:
+    """Coarse graph: an edge between two aggregates weighs the sum of the fine edge weights between them."""
+    nc = len(ident)
+    src = np.repeat(np.arange(G.n, dtype=np.int64), G.deg)
+    A = agg[src]
+    B = agg[G.adj]
+    cross = A != B
+    key = A[cross] * max(nc, 1) + B[cross]
+    uniq, inv = np.unique(key, return_inverse=True)
+    w = np.zeros(len(uniq), dtype=np.int64)
+    np.add.at(w, inv, G.wgt[cross])
+    csrc = uniq // max(nc, 1)
+    xadj = np.zeros(nc + 1, dtype=np.int64)
+    np.cumsum(np.bincount(csrc, minlength=nc), out=xadj[1:])
+    return LevelGraph(nc, xadj, uniq % max(nc, 1), w, ident)
+
+
+def expand(G: LevelGraph, order_up, children) -> list:
+    """Emit the vertices of G grouped by upper vertex in ``order_up`` (step 6 of the module notes)."""
+    n = G.n
+    xadj = G.xadj.tolist()
+    adj = G.adj.tolist()
+    wgt = G.wgt.tolist()
+    deg = G.deg.tolist()
+    ident = G.ident.tolist()
+    wp = [0] * n
+    placed = [False] * n
+    group = [-1] * n
+    out = []
+    for gi, U in enumerate(order_up):
+        S = children[U]
+        for v in S:
+            group[v] = gi
+        left = len(S)
+        while left:
+            s = min((v for v in S if not placed[v]), key=lambda v: (-wp[v], deg[v], ident[v]))
+            placed[s] = True
+            queue = [s]
+            head = 0
+            while head < len(queue):
+                u = queue[head]
+                head += 1
+                out.append(u)
+                left -= 1
+                cand = []
+                for p in range(xadj[u], xadj[u + 1]):
+                    v = adj[p]
+                    wp[v] += wgt[p]
+                    if group[v] == gi and not placed[v]:
+                        cand.append((-wgt[p], deg[v], ident[v], v))
+                cand.sort()
+                for c in cand:
+                    placed[c[3]] = True
+                    queue.append(c[3])
+    return out
+
+
+def running_counts(sizes) -> np.ndarray:
+    """[0, s0, s0+s1, ...] — the pointer encoding of Section 2.2 / Fig. 1."""
+    out = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(np.asarray(sizes, dtype=np.int64), out=out[1:])
+    return out
+
+
+def group_from_sizes(sr_sizes, ssr_sizes):
+    """(sr_ptr, ssr_ptr) from explicit group sizes: rows per SR, SRs per SSR."""
+    sr_ptr = running_counts(sr_sizes)
+    ssr_ptr = running_counts(ssr_sizes)
+    if ssr_ptr[-1] != len(sr_sizes):
+        raise ValueError("SSR sizes must add up to the number of SRs")
+    return sr_ptr, ssr_ptr
+
+
+def bandk_v1(row_ptr, col_idx, srs: int, ssrs: int):
+    """Band-k with k = 3.  Returns ``(perm, sr_ptr, ssr_ptr)`` with perm[new] = old."""
+    if srs < 1 or ssrs < 1:
+        raise ValueError("SRS and SSRS must be >= 1")
+    G0 = graph_from_csr(row_ptr, col_idx)
+    if G0.n == 0:
+        return np.zeros(0, np.int64), np.zeros(1, np.int64), np.zeros(1, np.int64)
+    agg1, ch1, id1 = aggregate(G0, srs)
+    G1 = quotient(G0, agg1, id1)
+    agg2, ch2, id2 = aggregate(G1, ssrs)
+    G2 = quotient(G1, agg2, id2)
+    order2 = reverse_cuthill_mckee(G2)
+    order1 = expand(G1, order2, ch2)
+    perm = expand(G0, order1, ch1)
+    sr_ptr = running_counts([len(ch1[s]) for s in order1])
+    ssr_ptr = running_counts([len(ch2[t]) for t in order2])
+    return np.asarray(perm, dtype=np.int64), sr_ptr, ssr_ptr
+
+
+def chunked(perm, srs: int, ssrs: int):
+    """SRs of SRS consecutive rows in ``perm`` order, SSRs of SSRS consecutive SRs (last ones may be short)."""
+    n = len(perm)
+    nsr = -(-n // srs) if n else 0
+    sr_sizes = [min(srs, n - s * srs) for s in range(nsr)]
+    nssr = -(-nsr // ssrs) if nsr else 0
+    ssr_sizes = [min(ssrs, nsr - t * ssrs) for t in range(nssr)]
+    return np.asarray(perm, dtype=np.int64), running_counts(sr_sizes), running_counts(ssr_sizes)
+
+
+def reorder_none(n: int, srs: int, ssrs: int):
+    return chunked(np.arange(n, dtype=np.int64), srs, ssrs)
+
+
+def reorder_rcm(row_ptr, col_idx, srs: int, ssrs: int):
+    return chunked(reverse_cuthill_mckee(graph_from_csr(row_ptr, col_idx)), srs, ssrs)
+
+
+def apply_permutation(row_ptr, col_idx, vals, perm):
+    """A' = P A P^T with A'[i', j'] = A[perm[i'], perm[j']]; columns sorted within rows.
+
+    Returns ``(row_ptr', col_idx', vals', vmap)`` where vmap[k'] is the position
+    of entry k' in the input arrays (the values are moved, never recomputed).
+    """
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col_idx = np.asarray(col_idx, dtype=np.int64)
+    perm = np.asarray(perm, dtype=np.int64)
+    n = len(perm)
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n)
+    lengths = np.diff(row_ptr)[perm]
+    new_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lengths, out=new_ptr[1:])
+    new_row = np.repeat(np.arange(n, dtype=np.int64), lengths)
+    src = row_ptr[perm][new_row] + (np.arange(new_ptr[-1]) - new_ptr[new_row])
+    new_col = iperm[col_idx[src]]
+    o = np.lexsort((new_col, new_row))
+    vmap = src[o]
+    return new_ptr, new_col[o], np.asarray(vals)[vmap], vmap
+
+
+def bandwidth(row_ptr, col_idx) -> int:
+    """max |i - j| over stored entries."""
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    n = len(row_ptr) - 1
+    if row_ptr[-1] == 0:
+        return 0
+    rows = np.repeat(np.arange(n), np.diff(row_ptr))
+    return int(np.max(np.abs(rows - np.asarray(col_idx, dtype=np.int64))))

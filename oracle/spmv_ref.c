@@ -1,0 +1,68 @@
+/*
+ * Oracle: plain FP64 CSR sparse matrix-vector product and its adjoint in C —
+ * TEST INFRASTRUCTURE ONLY (host timing of the oracle and a second check of
+ * the Python oracle).  Shares nothing with the library.
+ *
+ * Forward (Section 1 definition of SpMV over the CSR arrays of Section 2.1):
+ *   y_i = sum over k in [row_ptr[i], row_ptr[i+1]) of vals[k] * x[col_idx[k]],
+ * each row summed from 0.0 in storage order; rows are split over OpenMP
+ * threads with a static schedule, as the paper runs its CPU kernels
+ * (Section 5.2).
+ *
+ * Adjoint: grad_x[col_idx[k]] += vals[k] * g[i] for every stored entry in
+ * storage order (serial: a plain scatter), grad_vals[k] = g[i] * x[col_idx[k]].
+ *
+ * Pins: tests/test_oracle_cref.py (dense brute force, Laplacian times ones).
+ */
+#include <stdint.h>
+#include <string.h>
+#include <omp.h>
+
+void oracle_spmv_f64(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                     const double *vals, const double *x, double *y)
+{
+    int32_t i;
+#pragma omp parallel for schedule(static)
+    for (i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+            acc += vals[k] * x[col_idx[k]];
+        y[i] = acc;
+    }
+}
+
+void oracle_spmv_adjoint_f64(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                             const double *vals, const double *x, const double *g,
+                             double *grad_x, double *grad_vals)
+{
+    memset(grad_x, 0, sizeof(double) * (size_t)n);
+    for (int32_t i = 0; i < n; ++i) {
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            grad_x[col_idx[k]] += vals[k] * g[i];
+            grad_vals[k] = g[i] * x[col_idx[k]];
+        }
+    }
+}
+
+int oracle_threads(void) { return omp_get_max_threads(); }
+
+/* Runs the forward product `reps` times back to back and returns the wall seconds. */
+double oracle_time_spmv_f64(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                            const double *vals, const double *x, double *y, int reps)
+{
+    double t0 = omp_get_wtime();
+    for (int r = 0; r < reps; ++r)
+        oracle_spmv_f64(n, row_ptr, col_idx, vals, x, y);
+    return omp_get_wtime() - t0;
+}
+
+/* Runs the adjoint `reps` times and returns the wall seconds. */
+double oracle_time_adjoint_f64(int32_t n, const int32_t *row_ptr, const int32_t *col_idx,
+                               const double *vals, const double *x, const double *g,
+                               double *grad_x, double *grad_vals, int reps)
+{
+    double t0 = omp_get_wtime();
+    for (int r = 0; r < reps; ++r)
+        oracle_spmv_adjoint_f64(n, row_ptr, col_idx, vals, x, g, grad_x, grad_vals);
+    return omp_get_wtime() - t0;
+}
