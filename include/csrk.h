@@ -1,0 +1,240 @@
+/*
+ * csrk.h — C ABI of the CSR-k sparse matrix-vector library for AMD Instinct
+ * MI355X (gfx950).
+ *
+ * The operation is y = A x for a square sparse matrix A held in CSR-k form
+ * (Lane & Booth, "Heterogeneous Sparse Matrix-Vector Multiplication via
+ * Compressed Sparse Row Format"): plain CSR arrays (row_ptr, col_idx, vals;
+ * Section 2.1) of the reordered matrix plus two pointer arrays, sr_ptr
+ * (running count of rows per super-row) and ssr_ptr (running count of
+ * super-rows per super-super-row) (Section 2.2, Fig. 1).  The library builds
+ * the reordering and grouping on the host (Band-k, Section 2.2), picks the
+ * group sizes with a constant-time model (Section 4.1), and runs the product,
+ * its adjoint and batched multi-right-hand-side forms in HIP kernels.
+ *
+ * Conventions shared by every call:
+ *  - Every call returns a csrk_status and never throws across the ABI.  On
+ *    failure csrk_last_error_detail() returns a thread-local text.
+ *  - Indices are 32-bit (Section 2.1): n < 2^31 and nnz < 2^31.
+ *  - "perm" maps reordered to input rows: perm[new] = old.  The reordered
+ *    matrix is A' = P A P^T, A'[i', j'] = A[perm[i'], perm[j']].  Vectors in
+ *    "permuted space" are indexed by reordered rows: x'[i'] = x[perm[i']].
+ *  - Device pointers are HIP device addresses; streams are hipStream_t passed
+ *    as void* (NULL = the default stream).  Device calls are enqueued
+ *    asynchronously on that stream and never synchronise implicitly.
+ *  - Blocks of right-hand sides are row-major n x nrhs.
+ *  - A handle is immutable after it is built; concurrent device calls on one
+ *    handle from different streams are safe.  csrk_destroy must not overlap
+ *    calls still in flight (synchronise the stream first).
+ */
+#ifndef CSRK_H
+#define CSRK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum csrk_status {
+    CSRK_OK = 0,
+    CSRK_ERR_ARG = 1,          /* bad argument: null pointer, size <= 0 where forbidden, bad enum, misaligned pointer */
+    CSRK_ERR_NOT_SQUARE = 2,   /* reserved: the API only takes square matrices (n rows, columns < n) */
+    CSRK_ERR_BAD_ROWPTR = 3,   /* row_ptr[0] != 0, decreasing, or row_ptr[n] != nnz */
+    CSRK_ERR_COL_RANGE = 4,    /* a column index outside [0, n) */
+    CSRK_ERR_DUPLICATE = 5,    /* the same column twice in one row */
+    CSRK_ERR_ALLOC = 6,        /* host or device allocation failed */
+    CSRK_ERR_DEVICE = 7,       /* a HIP runtime error, or no GPU */
+    CSRK_ERR_UNSUPPORTED = 8   /* valid but not supported (e.g. device call on a host-only handle) */
+} csrk_status;
+
+/* Storage type of the matrix values.  F64 pairs with FP64 vectors and FP64
+ * accumulation; F32 and BF16 pair with FP32 vectors and FP32 accumulation. */
+typedef enum csrk_dtype { CSRK_F64 = 0, CSRK_F32 = 1, CSRK_BF16 = 2 } csrk_dtype;
+
+/* Size models.  VOLTA and AMPERE are the paper's fitted formulas (Section 4.1);
+ * MI355X is this library's fit of the same form for gfx950. */
+typedef enum csrk_model { CSRK_MODEL_MI355X = 0, CSRK_MODEL_VOLTA = 1, CSRK_MODEL_AMPERE = 2 } csrk_model;
+
+/* Row orderings: Band-k (Section 2.2; this library's deterministic reading),
+ * reverse Cuthill-McKee of the symmetrised pattern, or the input order. */
+typedef enum csrk_reorder { CSRK_REORDER_BANDK = 0, CSRK_REORDER_RCM = 1, CSRK_REORDER_NONE = 2 } csrk_reorder;
+
+/* Tuning parameters.  srs = rows per super-row (SRS), ssrs = super-rows per
+ * super-super-row (SSRS) (Section 4.1).  lanes_per_row (1, 2, 4, ..., 64) is
+ * the number of wavefront lanes that reduce one row; waves_per_wg (1..16) the
+ * wavefronts per workgroup.  k must be 3. */
+typedef struct csrk_params {
+    int32_t k;
+    int32_t srs;
+    int32_t ssrs;
+    int32_t lanes_per_row;
+    int32_t waves_per_wg;
+    int32_t reorder;  /* csrk_reorder */
+} csrk_params;
+
+/* Statistics of a built handle (Section 5.3 and Table 1 quantities). */
+typedef struct csrk_info {
+    int32_t n;
+    int64_t nnz;
+    int32_t nsr;              /* number of super-rows */
+    int32_t nssr;             /* number of super-super-rows */
+    double rdensity;          /* nnz / n (Section 4.1) */
+    double row_variance;      /* variance of nonzeros per row (Section 5.3) */
+    int32_t max_row;          /* maximum nonzeros in a row (Table 1 MAX) */
+    int32_t bandwidth_input;  /* max |i - j| of the input */
+    int32_t bandwidth;        /* max |i - j| after reordering */
+    double symmetry;          /* fraction of off-diagonal entries whose mirror is stored (Table 1 SY) */
+    int32_t max_sr_nnz;       /* largest nonzero count of a super-row */
+    int32_t max_ssr_rows;     /* largest row count of a super-super-row */
+    int32_t on_device;        /* 1 when device arrays exist */
+    int32_t store;            /* csrk_dtype of the device values (valid when on_device) */
+    csrk_params params;
+} csrk_info;
+
+typedef struct csrk_matrix *csrk_handle;
+typedef struct csrk_batch_s *csrk_batch;
+
+/* Text of a status code (static storage). */
+const char *csrk_status_string(csrk_status s);
+
+/* Thread-local detail of the last failure on this thread ("" if none). */
+const char *csrk_last_error_detail(void);
+
+/*
+ * csrk_tune — constant-time choice of the tuning parameters from n and nnz
+ * alone (rdensity = nnz / n; Section 4.1).  VOLTA/AMPERE reproduce the
+ * paper's formulas: round-half-up logarithmic fits and the per-case
+ * adjustments, "SRSS" read as SSRS, results clamped to >= 1.  MI355X uses
+ * this library's constants of the same form.  O(1), no allocation.
+ * Errors: CSRK_ERR_ARG for n <= 0, nnz <= 0, unknown model or out == NULL.
+ */
+csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out);
+
+/*
+ * csrk_build_host — validate the CSR input, build the symmetrised graph,
+ * reorder (Band-k / RCM / none), apply the symmetric permutation (columns
+ * sorted within rows) and form sr_ptr / ssr_ptr (Section 2.2).  Host only: no
+ * HIP call.  row_ptr[n+1], col_idx[nnz] and vals[nnz] (FP64, may be NULL for
+ * a pattern-only build, values then 0) are borrowed for the call and copied.
+ * Columns may be unsorted within a row; duplicates are rejected.  p == NULL
+ * uses csrk_tune(n, nnz, CSRK_MODEL_MI355X).  The result is deterministic:
+ * the same input gives a bit-identical structure.
+ * Errors: CSRK_ERR_ARG, CSRK_ERR_BAD_ROWPTR, CSRK_ERR_COL_RANGE,
+ * CSRK_ERR_DUPLICATE, CSRK_ERR_ALLOC.
+ */
+csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                            const double *vals, const csrk_params *p, csrk_handle *out);
+
+/*
+ * csrk_build_from_groups — like csrk_build_host but with a caller-given
+ * ordering perm[n] (perm[new] = old) and grouping: nsr super-rows of
+ * sr_sizes[s] >= 1 rows each (sum = n) and nssr super-super-rows of
+ * ssr_sizes[t] >= 1 super-rows each (sum = nsr).  This is how uneven groups
+ * such as those of Fig. 1 are expressed.
+ */
+csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                   const double *vals, const int32_t *perm, int32_t nsr, const int32_t *sr_sizes,
+                                   int32_t nssr, const int32_t *ssr_sizes, const csrk_params *p, csrk_handle *out);
+
+/*
+ * csrk_upload — copy a host-built handle's arrays to the current HIP device
+ * and convert the values to `store` there (FP64 -> FP32 round to nearest
+ * even; BF16 = BF16(FP32(v)), both steps round to nearest even).  Synchronous.
+ * Calling it again replaces the device copy.  Errors: CSRK_ERR_DEVICE,
+ * CSRK_ERR_ALLOC, CSRK_ERR_ARG.
+ */
+csrk_status csrk_upload(csrk_handle h, csrk_dtype store);
+
+/* csrk_build = csrk_build_host followed by csrk_upload. */
+csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                       const csrk_params *p, csrk_dtype store, csrk_handle *out);
+
+/* Statistics and parameters of a handle. */
+csrk_status csrk_get_info(csrk_handle h, csrk_info *out);
+
+/*
+ * csrk_copy_structure — copy the host structure into caller buffers; any
+ * pointer may be NULL.  perm[n], row_ptr[n+1], col_idx[nnz] and vals[nnz]
+ * (FP64 master values) describe A' as plain CSR, which is what keeps CSR-k
+ * readable by any CSR consumer (Section 2.2); vmap[nnz] gives the input
+ * position of each entry of A'; sr_ptr[nsr+1], ssr_ptr[nssr+1].
+ */
+csrk_status csrk_copy_structure(csrk_handle h, int32_t *perm, int32_t *row_ptr, int32_t *col_idx, double *vals,
+                                int64_t *vmap, int32_t *sr_ptr, int32_t *ssr_ptr);
+
+/*
+ * csrk_device_vals — the handle's device value array (nnz entries of the
+ * storage type, CSR-k order, 16-byte aligned).  Owned by the handle.
+ */
+csrk_status csrk_device_vals(csrk_handle h, void **vals_dev);
+
+/*
+ * csrk_spmv — y' = A' x' (Section 1 statement of SpMV on the CSR-k arrays;
+ * one super-super-row per workgroup, one super-row per wavefront, Section 3).
+ * vals_dev: NULL = the handle's values, else nnz values of the storage type
+ * in CSR-k order (16-byte aligned).  x_dev, y_dev: n x nrhs row-major in
+ * permuted space; FP64 for F64 storage, FP32 otherwise.  y must not alias x.
+ * Rows without nonzeros give 0.  nrhs >= 1.  Errors: CSRK_ERR_ARG,
+ * CSRK_ERR_UNSUPPORTED (host-only handle), CSRK_ERR_DEVICE (launch failure).
+ */
+csrk_status csrk_spmv(csrk_handle h, const void *vals_dev, const void *x_dev, void *y_dev, int32_t nrhs,
+                      void *stream);
+
+/*
+ * csrk_spmv_plain — the same product with a plain CSR kernel that ignores the
+ * super-row levels (rows spread over the grid in fixed-size blocks).  The
+ * baseline against which CSR-k is measured; same arguments as csrk_spmv.
+ */
+csrk_status csrk_spmv_plain(csrk_handle h, const void *vals_dev, const void *x_dev, void *y_dev, int32_t nrhs,
+                            void *stream);
+
+/*
+ * csrk_spmv_adjoint — gradients of L = <g', A' x'> (not in the paper):
+ * grad_x' = A'^T g' (n x nrhs, same type as x) and grad_vals'[k] =
+ * sum_c g'[row(k), c] x'[col(k), c] (nnz values in CSR-k order, FP64 for F64
+ * storage, FP32 otherwise).  Either output may be NULL to skip it.  grad_x is
+ * accumulated with device atomics, so its summation order (and last bits)
+ * may vary between runs; grad_vals is deterministic.  Same errors as
+ * csrk_spmv.
+ */
+csrk_status csrk_spmv_adjoint(csrk_handle h, const void *vals_dev, const void *x_dev, const void *g_dev,
+                              void *grad_x_dev, void *grad_vals_dev, int32_t nrhs, void *stream);
+
+/*
+ * csrk_permute — move a vector block between input and permuted space:
+ * direction 0: out[i', c] = in[perm[i'], c] (to permuted space);
+ * direction 1: out[perm[i'], c] = in[i', c] (back to input order).
+ * elem_bytes is 4 or 8.  in and out must not alias.
+ */
+csrk_status csrk_permute(csrk_handle h, int32_t direction, const void *in_dev, void *out_dev, int32_t nrhs,
+                         int32_t elem_bytes, void *stream);
+
+/* Free the handle and its host and device memory. */
+csrk_status csrk_destroy(csrk_handle h);
+
+/*
+ * Batched forms (not in the paper): many matrices of uneven size, each with
+ * an n_b x nrhs block, in one persistent launch over a work list of
+ * (matrix, super-super-row) items.  All handles must be on the device with
+ * the same storage type; they must outlive the batch.  The batch owns the
+ * work list and a device pointer table.
+ */
+csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_batch *out);
+
+/* y_b = A_b x_b for every b.  vals/x/y are arrays of `count` device pointers
+ * (vals may be NULL, or hold NULL entries, for the handles' own values). */
+csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *const *x, void *const *y, int32_t nrhs,
+                            void *stream);
+
+/* Adjoint of every product of the batch; grad_x / grad_vals arrays may be NULL. */
+csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const void *const *x, const void *const *g,
+                                    void *const *grad_x, void *const *grad_vals, int32_t nrhs, void *stream);
+
+csrk_status csrk_batch_destroy(csrk_batch b);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSRK_H */

@@ -1,0 +1,606 @@
+// C ABI of the CSR-k library (include/csrk.h): handles, argument checks,
+// status mapping, device upload and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/csrk.h"
+#include "device/launch.hpp"
+#include "host/host.hpp"
+
+using csrk::Error;
+
+struct csrk_matrix {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    csrk_params params{};
+    std::vector<int32_t> perm, row_ptr, col_idx, sr_ptr, ssr_ptr;
+    std::vector<int64_t> vmap;
+    std::vector<double> vals;
+    csrk::Stats in_stats, out_stats;
+    int32_t max_sr_nnz = 0, max_ssr_rows = 0;
+    // device side
+    bool on_device = false;
+    csrk_dtype store = CSRK_F64;
+    int device = -1;
+    int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_sr_ptr = nullptr, *d_ssr_ptr = nullptr, *d_perm = nullptr;
+    void *d_vals = nullptr;
+};
+
+struct csrk_batch_s {
+    std::vector<csrk_handle> handles;
+    csrk_dtype store = CSRK_F64;
+    int device = -1;
+    int32_t nitems = 0, max_n = 0;
+    int2 *d_items = nullptr;
+    // Descriptor tables on the device (forward, adjoint) and the host copies
+    // they were written from; a call re-uploads only when its pointers change.
+    csrk::dev::MatDesc *d_descs[2] = {nullptr, nullptr};
+    std::vector<csrk::dev::MatDesc> last[2];
+    bool last_valid[2] = {false, false};
+    csrk::dev::Shape shape;
+    int cus = 0;
+};
+
+namespace {
+
+thread_local std::string g_detail;
+
+void set_detail(const std::string &s) { g_detail = s; }
+
+template <typename F>
+csrk_status guard(F &&f) {
+    try {
+        g_detail.clear();
+        return f();
+    } catch (const Error &e) {
+        set_detail(e.detail);
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_detail("host allocation failed");
+        return CSRK_ERR_ALLOC;
+    } catch (const std::exception &e) {
+        set_detail(e.what());
+        return CSRK_ERR_ARG;
+    }
+}
+
+void hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return;
+    if (e == hipErrorOutOfMemory) throw Error{CSRK_ERR_ALLOC, std::string(what) + ": " + hipGetErrorString(e)};
+    throw Error{CSRK_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+size_t dtype_bytes(csrk_dtype d) { return d == CSRK_F64 ? 8 : d == CSRK_F32 ? 4 : 2; }
+
+// Makes the handle's device current for the scope of a call.
+struct DeviceScope {
+    int prev = -1;
+    explicit DeviceScope(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (dev >= 0 && dev != prev) hip_check(hipSetDevice(dev), "hipSetDevice");
+    }
+    ~DeviceScope() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+void free_device(csrk_matrix *h) {
+    if (!h->on_device) return;
+    DeviceScope ds(h->device);
+    for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
+                    (void *)h->d_perm, h->d_vals})
+        if (p) (void)hipFree(p);
+    h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
+    h->d_vals = nullptr;
+    h->on_device = false;
+}
+
+template <typename T>
+T *upload_array(const std::vector<T> &v, const char *what) {
+    T *d = nullptr;
+    hip_check(hipMalloc(&d, std::max<size_t>(1, v.size()) * sizeof(T)), what);
+    if (!v.empty()) {
+        hipError_t e = hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(d);
+            hip_check(e, what);
+        }
+    }
+    return d;
+}
+
+void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                 csrk::Grouping &&gr) {
+    csrk::Permuted pm = csrk::permute(h->n, row_ptr, col_idx, vals, gr.perm);
+    h->perm = std::move(gr.perm);
+    h->sr_ptr = std::move(gr.sr_ptr);
+    h->ssr_ptr = std::move(gr.ssr_ptr);
+    h->row_ptr = std::move(pm.row_ptr);
+    h->col_idx = std::move(pm.col_idx);
+    h->vals = std::move(pm.vals);
+    h->vmap = std::move(pm.vmap);
+    h->in_stats = csrk::row_stats(h->n, row_ptr, col_idx, false);
+    h->out_stats = csrk::row_stats(h->n, h->row_ptr.data(), h->col_idx.data(), true);
+    h->max_sr_nnz = 0;
+    for (size_t s = 0; s + 1 < h->sr_ptr.size(); ++s)
+        h->max_sr_nnz = std::max(h->max_sr_nnz, h->row_ptr[h->sr_ptr[s + 1]] - h->row_ptr[h->sr_ptr[s]]);
+    h->max_ssr_rows = 0;
+    for (size_t t = 0; t + 1 < h->ssr_ptr.size(); ++t)
+        h->max_ssr_rows = std::max(h->max_ssr_rows, h->sr_ptr[h->ssr_ptr[t + 1]] - h->sr_ptr[h->ssr_ptr[t]]);
+}
+
+csrk_params resolve_params(int32_t n, int64_t nnz, const csrk_params *p) {
+    csrk_params q{};
+    if (p) {
+        q = *p;
+    } else {
+        if (n == 0 || nnz == 0) {
+            q = csrk_params{3, 1, 1, 1, 4, CSRK_REORDER_BANDK};
+        } else if (csrk::tune(n, nnz, CSRK_MODEL_MI355X, &q) != CSRK_OK) {
+            throw Error{CSRK_ERR_ARG, "tuning failed"};
+        }
+    }
+    csrk::check_params(q);
+    return q;
+}
+
+csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
+    csrk::dev::Arrays a;
+    a.n = h->n;
+    a.nnz = h->nnz;
+    a.nsr = static_cast<int32_t>(h->sr_ptr.size()) - 1;
+    a.nssr = static_cast<int32_t>(h->ssr_ptr.size()) - 1;
+    a.row_ptr = h->d_row_ptr;
+    a.col_idx = h->d_col_idx;
+    a.sr_ptr = h->d_sr_ptr;
+    a.ssr_ptr = h->d_ssr_ptr;
+    a.perm = h->d_perm;
+    return a;
+}
+
+void need_device(const csrk_matrix *h) {
+    if (!h) throw Error{CSRK_ERR_ARG, "null handle"};
+    if (!h->on_device) throw Error{CSRK_ERR_UNSUPPORTED, "handle has no device arrays (call csrk_upload)"};
+}
+
+void check_vec(const void *p, const csrk_matrix *h, const char *name) {
+    if (h->n > 0 && !p) throw Error{CSRK_ERR_ARG, std::string(name) + " is NULL"};
+}
+
+const void *values_for(const csrk_matrix *h, const void *vals_dev) {
+    const void *v = vals_dev ? vals_dev : h->d_vals;
+    if (reinterpret_cast<uintptr_t>(v) % 16 != 0) throw Error{CSRK_ERR_ARG, "vals_dev must be 16-byte aligned"};
+    return v;
+}
+
+csrk::dev::Shape shape_of(const csrk_matrix *h) {
+    csrk::dev::Shape s;
+    s.lanes_per_row = h->params.lanes_per_row;
+    s.waves = h->params.waves_per_wg;
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *csrk_status_string(csrk_status s) {
+    switch (s) {
+    case CSRK_OK:
+        return "CSRK_OK";
+    case CSRK_ERR_ARG:
+        return "CSRK_ERR_ARG: invalid argument";
+    case CSRK_ERR_NOT_SQUARE:
+        return "CSRK_ERR_NOT_SQUARE: matrix is not square";
+    case CSRK_ERR_BAD_ROWPTR:
+        return "CSRK_ERR_BAD_ROWPTR: malformed row_ptr";
+    case CSRK_ERR_COL_RANGE:
+        return "CSRK_ERR_COL_RANGE: column index out of range";
+    case CSRK_ERR_DUPLICATE:
+        return "CSRK_ERR_DUPLICATE: duplicate column in a row";
+    case CSRK_ERR_ALLOC:
+        return "CSRK_ERR_ALLOC: allocation failed";
+    case CSRK_ERR_DEVICE:
+        return "CSRK_ERR_DEVICE: HIP device error";
+    case CSRK_ERR_UNSUPPORTED:
+        return "CSRK_ERR_UNSUPPORTED: operation not supported";
+    }
+    return "unknown csrk_status";
+}
+
+const char *csrk_last_error_detail(void) { return g_detail.c_str(); }
+
+csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
+    return guard([&] {
+        csrk_status s = csrk::tune(n, nnz, model, out);
+        if (s != CSRK_OK) set_detail("csrk_tune needs n > 0, nnz > 0, a known model and an output pointer");
+        return s;
+    });
+}
+
+csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                            const double *vals, const csrk_params *p, csrk_handle *out) {
+    return guard([&] {
+        if (!out) throw Error{CSRK_ERR_ARG, "out is NULL"};
+        *out = nullptr;
+        csrk::validate_csr(n, nnz, row_ptr, col_idx);
+        csrk_params q = resolve_params(n, nnz, p);
+        csrk::Grouping gr;
+        if (q.reorder == CSRK_REORDER_BANDK) {
+            gr = csrk::bandk(n, row_ptr, col_idx, q.srs, q.ssrs);
+        } else if (q.reorder == CSRK_REORDER_RCM) {
+            gr = csrk::rcm_chunked(n, row_ptr, col_idx, q.srs, q.ssrs);
+        } else {
+            std::vector<int32_t> id(n);
+            std::iota(id.begin(), id.end(), 0);
+            gr = csrk::chunked(std::move(id), q.srs, q.ssrs);
+        }
+        auto h = new csrk_matrix();
+        try {
+            h->n = n;
+            h->nnz = nnz;
+            h->params = q;
+            finish_host(h, row_ptr, col_idx, vals, std::move(gr));
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                                   const double *vals, const int32_t *perm, int32_t nsr, const int32_t *sr_sizes,
+                                   int32_t nssr, const int32_t *ssr_sizes, const csrk_params *p, csrk_handle *out) {
+    return guard([&] {
+        if (!out) throw Error{CSRK_ERR_ARG, "out is NULL"};
+        *out = nullptr;
+        csrk::validate_csr(n, nnz, row_ptr, col_idx);
+        if (n > 0 && !perm) throw Error{CSRK_ERR_ARG, "perm is NULL"};
+        csrk_params q = resolve_params(n, nnz, p);
+        csrk::Grouping gr = csrk::from_sizes(std::vector<int32_t>(perm, perm + n), sr_sizes, nsr, ssr_sizes, nssr);
+        auto h = new csrk_matrix();
+        try {
+            h->n = n;
+            h->nnz = nnz;
+            h->params = q;
+            finish_host(h, row_ptr, col_idx, vals, std::move(gr));
+        } catch (...) {
+            delete h;
+            throw;
+        }
+        *out = h;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
+    return guard([&] {
+        if (!h) throw Error{CSRK_ERR_ARG, "null handle"};
+        if (store != CSRK_F64 && store != CSRK_F32 && store != CSRK_BF16) throw Error{CSRK_ERR_ARG, "unknown dtype"};
+        int count = 0;
+        if (hipGetDeviceCount(&count) != hipSuccess || count == 0) throw Error{CSRK_ERR_DEVICE, "no HIP device"};
+        free_device(h);
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        h->device = dev;
+        h->store = store;
+        try {
+            h->d_row_ptr = upload_array(h->row_ptr, "row_ptr");
+            h->d_col_idx = upload_array(h->col_idx, "col_idx");
+            h->d_sr_ptr = upload_array(h->sr_ptr, "sr_ptr");
+            h->d_ssr_ptr = upload_array(h->ssr_ptr, "ssr_ptr");
+            h->d_perm = upload_array(h->perm, "perm");
+            hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
+            h->on_device = true;
+            if (h->nnz > 0) {
+                double *tmp = upload_array(h->vals, "vals (staging)");
+                hipError_t e = csrk::dev::convert_values(tmp, h->d_vals, h->nnz, store, nullptr);
+                hipError_t e2 = hipDeviceSynchronize();
+                (void)hipFree(tmp);
+                hip_check(e, "value conversion");
+                hip_check(e2, "value conversion");
+            }
+        } catch (...) {
+            h->on_device = true;
+            free_device(h);
+            throw;
+        }
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                       const csrk_params *p, csrk_dtype store, csrk_handle *out) {
+    csrk_status s = csrk_build_host(n, nnz, row_ptr, col_idx, vals, p, out);
+    if (s != CSRK_OK) return s;
+    s = csrk_upload(*out, store);
+    if (s != CSRK_OK) {
+        std::string keep = g_detail;
+        csrk_destroy(*out);
+        *out = nullptr;
+        g_detail = keep;
+    }
+    return s;
+}
+
+csrk_status csrk_get_info(csrk_handle h, csrk_info *out) {
+    return guard([&] {
+        if (!h || !out) throw Error{CSRK_ERR_ARG, "null argument"};
+        csrk_info i{};
+        i.n = h->n;
+        i.nnz = h->nnz;
+        i.nsr = static_cast<int32_t>(h->sr_ptr.size()) - 1;
+        i.nssr = static_cast<int32_t>(h->ssr_ptr.size()) - 1;
+        i.rdensity = h->out_stats.rdensity;
+        i.row_variance = h->out_stats.row_variance;
+        i.max_row = h->out_stats.max_row;
+        i.bandwidth_input = h->in_stats.bandwidth;
+        i.bandwidth = h->out_stats.bandwidth;
+        i.symmetry = h->out_stats.symmetry;
+        i.max_sr_nnz = h->max_sr_nnz;
+        i.max_ssr_rows = h->max_ssr_rows;
+        i.on_device = h->on_device ? 1 : 0;
+        i.store = h->store;
+        i.params = h->params;
+        *out = i;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_copy_structure(csrk_handle h, int32_t *perm, int32_t *row_ptr, int32_t *col_idx, double *vals,
+                                int64_t *vmap, int32_t *sr_ptr, int32_t *ssr_ptr) {
+    return guard([&] {
+        if (!h) throw Error{CSRK_ERR_ARG, "null handle"};
+        auto cp = [](auto *dst, const auto &v) {
+            if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(v[0]));
+        };
+        cp(perm, h->perm);
+        cp(row_ptr, h->row_ptr);
+        cp(col_idx, h->col_idx);
+        cp(vals, h->vals);
+        cp(vmap, h->vmap);
+        cp(sr_ptr, h->sr_ptr);
+        cp(ssr_ptr, h->ssr_ptr);
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_device_vals(csrk_handle h, void **vals_dev) {
+    return guard([&] {
+        need_device(h);
+        if (!vals_dev) throw Error{CSRK_ERR_ARG, "null output"};
+        *vals_dev = h->d_vals;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_spmv(csrk_handle h, const void *vals_dev, const void *x_dev, void *y_dev, int32_t nrhs,
+                      void *stream) {
+    return guard([&] {
+        need_device(h);
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        check_vec(x_dev, h, "x");
+        check_vec(y_dev, h, "y");
+        if (h->n > 0 && x_dev == y_dev) throw Error{CSRK_ERR_ARG, "y must not alias x"};
+        const void *v = values_for(h, vals_dev);
+        DeviceScope ds(h->device);
+        hip_check(csrk::dev::spmv(arrays_of(h), h->store, v, x_dev, y_dev, nrhs, shape_of(h),
+                                  static_cast<hipStream_t>(stream)),
+                  "csrk_spmv launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_spmv_plain(csrk_handle h, const void *vals_dev, const void *x_dev, void *y_dev, int32_t nrhs,
+                            void *stream) {
+    return guard([&] {
+        need_device(h);
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        check_vec(x_dev, h, "x");
+        check_vec(y_dev, h, "y");
+        if (h->n > 0 && x_dev == y_dev) throw Error{CSRK_ERR_ARG, "y must not alias x"};
+        const void *v = values_for(h, vals_dev);
+        DeviceScope ds(h->device);
+        hip_check(csrk::dev::spmv_plain(arrays_of(h), h->store, v, x_dev, y_dev, nrhs, shape_of(h),
+                                        static_cast<hipStream_t>(stream)),
+                  "csrk_spmv_plain launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_spmv_adjoint(csrk_handle h, const void *vals_dev, const void *x_dev, const void *g_dev,
+                              void *grad_x_dev, void *grad_vals_dev, int32_t nrhs, void *stream) {
+    return guard([&] {
+        need_device(h);
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        check_vec(g_dev, h, "g");
+        if (grad_vals_dev) check_vec(x_dev, h, "x");
+        if (!grad_x_dev && !grad_vals_dev) return CSRK_OK;
+        if (grad_x_dev && h->n > 0 && (grad_x_dev == g_dev || grad_x_dev == x_dev))
+            throw Error{CSRK_ERR_ARG, "grad_x must not alias x or g"};
+        const void *v = values_for(h, vals_dev);
+        DeviceScope ds(h->device);
+        hip_check(csrk::dev::adjoint(arrays_of(h), h->store, v, x_dev, g_dev, grad_x_dev, grad_vals_dev, nrhs,
+                                     shape_of(h), static_cast<hipStream_t>(stream)),
+                  "csrk_spmv_adjoint launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_permute(csrk_handle h, int32_t direction, const void *in_dev, void *out_dev, int32_t nrhs,
+                         int32_t elem_bytes, void *stream) {
+    return guard([&] {
+        need_device(h);
+        if (direction != 0 && direction != 1) throw Error{CSRK_ERR_ARG, "direction must be 0 or 1"};
+        if (elem_bytes != 4 && elem_bytes != 8) throw Error{CSRK_ERR_ARG, "elem_bytes must be 4 or 8"};
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        check_vec(in_dev, h, "in");
+        check_vec(out_dev, h, "out");
+        if (h->n > 0 && in_dev == out_dev) throw Error{CSRK_ERR_ARG, "in and out must not alias"};
+        DeviceScope ds(h->device);
+        hip_check(csrk::dev::permute(arrays_of(h), direction, in_dev, out_dev, nrhs, elem_bytes,
+                                     static_cast<hipStream_t>(stream)),
+                  "csrk_permute launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_destroy(csrk_handle h) {
+    return guard([&] {
+        if (!h) return CSRK_OK;
+        free_device(h);
+        delete h;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_batch *out) {
+    return guard([&] {
+        if (!out || !handles || count < 1) throw Error{CSRK_ERR_ARG, "need count >= 1 handles and an output"};
+        *out = nullptr;
+        for (int32_t b = 0; b < count; ++b) {
+            need_device(handles[b]);
+            if (handles[b]->store != handles[0]->store) throw Error{CSRK_ERR_ARG, "all handles need one storage type"};
+            if (handles[b]->device != handles[0]->device) throw Error{CSRK_ERR_ARG, "all handles need one device"};
+        }
+        auto bt = new csrk_batch_s();
+        try {
+            bt->handles.assign(handles, handles + count);
+            bt->store = handles[0]->store;
+            bt->device = handles[0]->device;
+            DeviceScope ds(bt->device);
+            std::vector<int2> items;
+            for (int32_t b = 0; b < count; ++b) {
+                const int32_t nssr = static_cast<int32_t>(handles[b]->ssr_ptr.size()) - 1;
+                for (int32_t t = 0; t < nssr; ++t) items.push_back(make_int2(b, t));
+                bt->max_n = std::max(bt->max_n, handles[b]->n);
+            }
+            if (items.size() > size_t(INT32_MAX)) throw Error{CSRK_ERR_ARG, "work list too long"};
+            bt->nitems = static_cast<int32_t>(items.size());
+            bt->d_items = upload_array(items, "batch work list");
+            for (int k = 0; k < 2; ++k)
+                hip_check(hipMalloc(&bt->d_descs[k], sizeof(csrk::dev::MatDesc) * size_t(count)), "batch descriptors");
+            // Batch-wide kernel shape: the first handle's lanes/waves, which
+            // the batch tuner makes uniform.
+            bt->shape = shape_of(handles[0]);
+            int cus = 0;
+            hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, bt->device), "CU count");
+            bt->cus = cus;
+        } catch (...) {
+            if (bt->d_items) (void)hipFree(bt->d_items);
+            for (auto *p : bt->d_descs)
+                if (p) (void)hipFree(p);
+            delete bt;
+            throw;
+        }
+        *out = bt;
+        return CSRK_OK;
+    });
+}
+
+namespace {
+
+csrk::dev::MatDesc *upload_descs(csrk_batch b, int which, const void *const *vals, const void *const *x, void *const *y, const void *const *g,
+                  void *const *gx, void *const *gv, hipStream_t st) {
+    const size_t count = b->handles.size();
+    std::vector<csrk::dev::MatDesc> d(count);
+    for (size_t i = 0; i < count; ++i) {
+        const csrk_matrix *h = b->handles[i];
+        csrk::dev::MatDesc &m = d[i];
+        std::memset(&m, 0, sizeof(m));
+        m.ssr_ptr = h->d_ssr_ptr;
+        m.sr_ptr = h->d_sr_ptr;
+        m.row_ptr = h->d_row_ptr;
+        m.col_idx = h->d_col_idx;
+        m.vals = values_for(h, vals ? vals[i] : nullptr);
+        m.x = x ? x[i] : nullptr;
+        m.y = y ? y[i] : nullptr;
+        m.g = g ? g[i] : nullptr;
+        m.gx = gx ? gx[i] : nullptr;
+        m.gv = gv ? gv[i] : nullptr;
+        m.nnz = h->nnz;
+        m.n = h->n;
+        m.nssr = static_cast<int32_t>(h->ssr_ptr.size()) - 1;
+    }
+    if (b->last_valid[which] && std::memcmp(d.data(), b->last[which].data(), count * sizeof(d[0])) == 0)
+        return b->d_descs[which];
+    // Pageable source: the runtime has consumed it when the call returns.  The
+    // copy is ordered after earlier kernels of the same stream that read the table.
+    hip_check(hipMemcpyAsync(b->d_descs[which], d.data(), count * sizeof(d[0]), hipMemcpyHostToDevice, st),
+              "batch descriptor upload");
+    b->last[which] = std::move(d);
+    b->last_valid[which] = true;
+    return b->d_descs[which];
+}
+
+int batch_grid(csrk_batch b, int nrhs, bool adj) {
+    const int per_cu = csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj);
+    const int64_t g = int64_t(b->cus) * per_cu;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, b->nitems)));
+}
+
+}  // namespace
+
+csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *const *x, void *const *y, int32_t nrhs,
+                            void *stream) {
+    return guard([&] {
+        if (!b || !x || !y) throw Error{CSRK_ERR_ARG, "null argument"};
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        for (size_t i = 0; i < b->handles.size(); ++i) {
+            check_vec(x[i], b->handles[i], "x");
+            check_vec(y[i], b->handles[i], "y");
+        }
+        DeviceScope ds(b->device);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        csrk::dev::MatDesc *descs = upload_descs(b, 0, vals, x, y, nullptr, nullptr, nullptr, st);
+        hip_check(csrk::dev::batch_forward(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
+                                           batch_grid(b, nrhs, false), st),
+                  "csrk_batch_spmv launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const void *const *x, const void *const *g,
+                                    void *const *grad_x, void *const *grad_vals, int32_t nrhs, void *stream) {
+    return guard([&] {
+        if (!b || !g) throw Error{CSRK_ERR_ARG, "null argument"};
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        if (!grad_x && !grad_vals) return CSRK_OK;
+        for (size_t i = 0; i < b->handles.size(); ++i) {
+            check_vec(g[i], b->handles[i], "g");
+            if (grad_vals) check_vec(x ? x[i] : nullptr, b->handles[i], "x");
+        }
+        DeviceScope ds(b->device);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        csrk::dev::MatDesc *descs = upload_descs(b, 1, vals, x, nullptr, g, grad_x, grad_vals, st);
+        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems,
+                                           static_cast<int32_t>(b->handles.size()), b->max_n, b->store, nrhs,
+                                           b->shape, batch_grid(b, nrhs, true), st),
+                  "csrk_batch_spmv_adjoint launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_batch_destroy(csrk_batch b) {
+    return guard([&] {
+        if (!b) return CSRK_OK;
+        DeviceScope ds(b->device);
+        if (b->d_items) (void)hipFree(b->d_items);
+        for (auto *p : b->d_descs)
+            if (p) (void)hipFree(p);
+        delete b;
+        return CSRK_OK;
+    });
+}
+
+}  // extern "C"

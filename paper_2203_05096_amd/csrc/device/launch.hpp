@@ -1,0 +1,69 @@
+// Launchers of the gfx950 kernels (device/kernels.hip).  C++ linkage, used
+// only by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../../include/csrk.h"
+
+namespace csrk {
+namespace dev {
+
+// Device arrays of one CSR-k matrix.
+struct Arrays {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    int32_t nsr = 0;
+    int32_t nssr = 0;
+    const int32_t *row_ptr = nullptr;
+    const int32_t *col_idx = nullptr;
+    const int32_t *sr_ptr = nullptr;
+    const int32_t *ssr_ptr = nullptr;
+    const int32_t *perm = nullptr;
+};
+
+// Per-matrix record of a batched launch (device-resident table).
+struct MatDesc {
+    const int32_t *ssr_ptr;
+    const int32_t *sr_ptr;
+    const int32_t *row_ptr;
+    const int32_t *col_idx;
+    const void *vals;
+    const void *x;
+    void *y;
+    const void *g;
+    void *gx;
+    void *gv;
+    int64_t nnz;
+    int32_t n;
+    int32_t nssr;
+};
+
+// Kernel-shape knobs: lanes per row in the reduction, wavefronts per workgroup.
+struct Shape {
+    int lanes_per_row = 1;
+    int waves = 4;
+};
+
+hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, int nrhs, Shape s,
+                hipStream_t st);
+hipError_t spmv_plain(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, int nrhs,
+                      Shape s, hipStream_t st);
+hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const void *x, const void *g, void *gx,
+                   void *gv, int nrhs, Shape s, hipStream_t st);
+hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st);
+hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtype store, hipStream_t st);
+
+// Batched persistent launches over `nitems` (matrix, super-super-row) items.
+hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
+                         Shape s, int grid, hipStream_t st);
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, int32_t nmat, int32_t max_n,
+                         csrk_dtype store, int nrhs, Shape s, int grid, hipStream_t st);
+
+// Workgroups per CU the batched kernels can keep resident (for sizing the grid).
+int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint);
+
+}  // namespace dev
+}  // namespace csrk

@@ -1,0 +1,120 @@
+// Host-side preprocessing of the CSR-k library: validation, the symmetrised
+// graph, orderings (weighted Cuthill-McKee, Band-k), the symmetric
+// permutation, grouping into super-rows / super-super-rows, statistics and
+// the constant-time size model.  Plain C++17, no HIP: it builds and is tested
+// on machines without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../../include/csrk.h"
+
+namespace csrk {
+
+// Error raised inside the host code; the C ABI turns it into a status.
+struct Error {
+    csrk_status status;
+    std::string detail;
+};
+
+// ---------------------------------------------------------------- graphs
+
+// Undirected weighted graph in CSR form.  Adjacency lists are sorted by
+// vertex index and hold each neighbour once.  ident[v] is the vertex's id for
+// tie-breaking: the smallest input row it stands for.  Vertices are numbered
+// in increasing ident, so comparing indices and comparing idents agree.
+struct Graph {
+    int32_t n = 0;
+    std::vector<int64_t> xadj;
+    std::vector<int32_t> adj;
+    std::vector<int64_t> wgt;
+    std::vector<int64_t> ident;
+    int64_t degree(int32_t v) const { return xadj[v + 1] - xadj[v]; }
+};
+
+// Grouping of the vertices of one level into coarse vertices.
+struct Aggregation {
+    int32_t ncoarse = 0;
+    std::vector<int32_t> owner;      // fine vertex -> coarse vertex
+    std::vector<int64_t> child_ptr;  // coarse vertex c owns children[child_ptr[c] .. child_ptr[c+1])
+    std::vector<int32_t> children;
+    std::vector<int64_t> ident;      // coarse vertex ids (smallest input row)
+};
+
+// G0: pattern of A + A^T without the diagonal, unit weights (Section 2.2 turns
+// the matrix into a graph; symmetrising is this library's reading).
+Graph graph_from_csr(int32_t n, const int32_t *row_ptr, const int32_t *col_idx);
+
+// Weighted Cuthill-McKee: repeated FIFO breadth-first searches started at the
+// unvisited vertex with the smallest (degree, id); a dequeued vertex's
+// unvisited neighbours are queued by (-edge weight, degree, id).
+std::vector<int32_t> cuthill_mckee(const Graph &g);
+
+// Consecutive chunks of `chunk` vertices of cuthill_mckee(g) (the last may be
+// shorter); coarse vertices numbered by increasing id.
+Aggregation aggregate(const Graph &g, int32_t chunk);
+
+// Quotient graph: coarse edge weight = sum of fine edge weights between the
+// two aggregates.
+Graph quotient(const Graph &g, const Aggregation &a);
+
+// Emit the fine vertices of each coarse vertex, coarse vertices taken in
+// `order_up`.  Inside a coarse vertex: start at the not-yet-emitted child with
+// the smallest (-wp, degree, id), wp = total edge weight to vertices already
+// emitted, then breadth-first search restricted to the children with the
+// Cuthill-McKee neighbour key; repeat until all children are emitted.
+std::vector<int32_t> expand(const Graph &g, const std::vector<int32_t> &order_up, const Aggregation &a);
+
+// Ordering + grouping result: perm[new] = old; sr_ptr / ssr_ptr running counts.
+struct Grouping {
+    std::vector<int32_t> perm;
+    std::vector<int32_t> sr_ptr;
+    std::vector<int32_t> ssr_ptr;
+};
+
+// Band-k with k = 3 (Section 2.2): coarsen by SRS, coarsen again by SSRS,
+// reverse Cuthill-McKee of the coarsest graph, expand twice.
+Grouping bandk(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t ssrs);
+
+// Fixed-size chunks over a given order (input order or RCM of G0).
+Grouping chunked(std::vector<int32_t> perm, int32_t srs, int32_t ssrs);
+Grouping rcm_chunked(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t ssrs);
+
+// Grouping from explicit sizes.
+Grouping from_sizes(std::vector<int32_t> perm, const int32_t *sr_sizes, int32_t nsr, const int32_t *ssr_sizes,
+                    int32_t nssr);
+
+// ---------------------------------------------------------------- CSR
+
+// Checks row_ptr / col_idx; throws Error with the matching status.
+void validate_csr(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx);
+
+// A' = P A P^T with columns sorted inside each row; vmap[k'] = input position.
+struct Permuted {
+    std::vector<int32_t> row_ptr;
+    std::vector<int32_t> col_idx;
+    std::vector<double> vals;
+    std::vector<int64_t> vmap;
+};
+Permuted permute(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
+                 const std::vector<int32_t> &perm);
+
+// Row statistics (Section 5.3 / Table 1).
+struct Stats {
+    double rdensity = 0, row_variance = 0, symmetry = 1;
+    int32_t max_row = 0, bandwidth = 0;
+};
+Stats row_stats(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, bool sorted_rows);
+int32_t bandwidth(int32_t n, const int32_t *row_ptr, const int32_t *col_idx);
+
+// ---------------------------------------------------------------- model
+
+// Constant-time size model (Section 4.1); see csrk_tune.
+csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out);
+
+// Sanity-checks parameters (throws Error CSRK_ERR_ARG).
+void check_params(const csrk_params &p);
+
+}  // namespace csrk

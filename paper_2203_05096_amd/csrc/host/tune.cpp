@@ -1,0 +1,102 @@
+// Constant-time size model (Section 4.1).
+//
+// The paper fits SSRS = round(a_s - b_s ln r) and SRS = round(a_r - b_r ln r)
+// by logarithmic regression over the best sizes of a sweep, rounds to nearest
+// with halves toward +infinity, then adjusts the sizes per row-density case
+// (r <= 8, <= 16, <= 32, > 32) to account for its block shapes.  The VOLTA and
+// AMPERE models below are the paper's constants and adjustments; MI355X is
+// this library's fit of the same form for its gfx950 kernels (one
+// super-super-row per workgroup, one super-row per wavefront), refitted from
+// measured sweeps.
+#include <cmath>
+
+#include "host.hpp"
+
+namespace csrk {
+
+namespace {
+
+int64_t round_half_up(double v) { return static_cast<int64_t>(std::floor(v + 0.5)); }
+
+int case_of(double r) {
+    if (r <= 8) return 1;
+    if (r <= 16) return 2;
+    if (r <= 32) return 3;
+    return 4;
+}
+
+// MI355X fit of the same logarithmic form.  SRS (rows per super-row) is sized
+// so one super-row's nonzeros fill a wavefront's LDS staging window; SSRS
+// (super-rows per workgroup) keeps every wavefront of the workgroup busy.
+constexpr double kMiSsrsA = 8.0, kMiSsrsB = 0.0;
+constexpr double kMiSrsA = 133.0, kMiSrsB = 35.5;
+
+int32_t clamp_size(int64_t v, int64_t hi) { return static_cast<int32_t>(std::max<int64_t>(1, std::min(v, hi))); }
+
+}  // namespace
+
+csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
+    if (!out || n <= 0 || nnz <= 0) return CSRK_ERR_ARG;
+    const double r = double(nnz) / double(n);
+    const double lr = std::log(r);
+    const int c = case_of(r);
+    int64_t ssrs, srs;
+    csrk_params p{};
+    p.k = 3;
+    p.reorder = CSRK_REORDER_BANDK;
+    switch (model) {
+    case CSRK_MODEL_VOLTA:
+        ssrs = round_half_up(8.900 - 1.25 * lr);
+        srs = round_half_up(10.146 - 1.50 * lr);
+        if (c == 2) {
+            ssrs = round_half_up(double(ssrs) * 1.5);
+            srs = ssrs * 2;
+        } else if (c == 3) {
+            ssrs = ssrs * 4;
+            srs = ssrs / 2 - ((ssrs % 2 != 0 && ssrs < 0) ? 1 : 0);
+        } else if (c == 4) {
+            ssrs = ssrs * 5;
+            srs = ssrs / 2 - ((ssrs % 2 != 0 && ssrs < 0) ? 1 : 0);
+        }
+        break;
+    case CSRK_MODEL_AMPERE:
+        ssrs = round_half_up(9.175 - 1.32 * lr);
+        srs = round_half_up(20.500 - 3.50 * lr);
+        if (c == 2) {
+            srs = ssrs * 4;
+        } else if (c == 3) {
+            ssrs = round_half_up(double(ssrs) * 2.5);
+            srs = ssrs * 3;
+        } else if (c == 4) {
+            ssrs = ssrs * 2;
+            srs = ssrs * 2;
+        }
+        break;
+    case CSRK_MODEL_MI355X:
+        ssrs = round_half_up(kMiSsrsA - kMiSsrsB * lr);
+        srs = round_half_up(kMiSrsA - kMiSrsB * lr);
+        break;
+    default:
+        return CSRK_ERR_ARG;
+    }
+    p.ssrs = clamp_size(ssrs, INT32_MAX);
+    p.srs = clamp_size(srs, INT32_MAX);
+    // Lanes that reduce one row: a row per lane while rows are short, wider
+    // groups as rows lengthen (the paper switches to an in-row parallel kernel
+    // above 8 nonzeros per row, Section 3).
+    p.lanes_per_row = r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 4 : r <= 128 ? 8 : 16;
+    p.waves_per_wg = 4;
+    *out = p;
+    return CSRK_OK;
+}
+
+void check_params(const csrk_params &p) {
+    if (p.k != 3) throw Error{CSRK_ERR_ARG, "only k = 3 is supported"};
+    if (p.srs < 1 || p.ssrs < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
+    const int L = p.lanes_per_row;
+    if (L < 1 || L > 64 || (L & (L - 1))) throw Error{CSRK_ERR_ARG, "lanes_per_row must be a power of two in 1..64"};
+    if (p.waves_per_wg < 1 || p.waves_per_wg > 16) throw Error{CSRK_ERR_ARG, "waves_per_wg must be in 1..16"};
+    if (p.reorder < CSRK_REORDER_BANDK || p.reorder > CSRK_REORDER_NONE) throw Error{CSRK_ERR_ARG, "unknown reorder"};
+}
+
+}  // namespace csrk

@@ -1,0 +1,160 @@
+"""GPU parity of the adjoint (grad_x = A^T g, grad_vals = g_i x_j) and of the autograd wrapper."""
+
+import numpy as np
+import pytest
+
+from gen import random_sparse, workload_c4
+from gpu_util import params, say, to_dev
+from oracle import adjoint as OA
+from oracle import precision as OP
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2203_05096_amd import _capi as C  # noqa: E402
+from paper_2203_05096_amd.matrix import CsrkMatrix, CsrkSpMV  # noqa: E402
+
+VEC = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
+U = {"f64": 2.0 ** -53, "f32": 2.0 ** -24, "bf16": 2.0 ** -24}
+
+
+def _build(A, store, p):
+    return CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store)
+
+
+def _adjoint(M, x, g):
+    """x, g in input order (float64, (n,) or (n, k)); returns (grad_x in input order, grad_vals in input order)."""
+    s = M.structure()
+    perm, vmap = s["perm"], s["vmap"]
+    xp, gp = x[perm], g[perm]
+    if M.store != "f64":
+        xp, gp = xp.astype(np.float32), gp.astype(np.float32)
+    gx, gv = M.adjoint(to_dev(xp, VEC[M.store]), to_dev(gp, VEC[M.store]))
+    torch.cuda.synchronize()
+    gx_in = np.empty_like(np.asarray(gx.double().cpu().numpy()))
+    gx_in[perm] = gx.double().cpu().numpy()
+    gv_in = np.empty(len(vmap), dtype=np.float64)
+    gv_in[vmap] = gv.double().cpu().numpy()
+    return gx_in, gv_in
+
+
+def _check_grad_x(gx, A, g, store, x_rounded, label):
+    ref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, g)
+    scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(g))
+    colcount = np.bincount(A.col_idx, minlength=A.n)
+    if ref.ndim == 2:
+        colcount = colcount[:, None]
+    if store == "f64":
+        beta = np.full(colcount.shape, 1e-12)
+    else:
+        beta = OP.forward_bound(np.maximum(colcount, 1), store, x_rounded, "f32")
+    err = np.abs(gx - ref)
+    assert np.all(err <= beta * scale), f"{label}: grad_x over bound by {np.max(err - beta * scale):.3e}"
+
+
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_adjoint_random_ragged(store):
+    A = random_sparse(4000, 6.0, seed=12, empty_row_frac=0.1)
+    if store == "f32":
+        A.vals = A.vals.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(12)
+    x, g = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    if store == "f32":
+        x, g = x.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    say("adjoint ragged", store)
+    M = _build(A, store, params(19, 4))
+    gx, gv = _adjoint(M, x, g)
+    ref_gv = OA.grad_vals(A.row_ptr, A.col_idx, x, g)
+    if store == "f32":
+        ref_gv = ref_gv.astype(np.float32).astype(np.float64)  # exact FP64 product rounded once = FP32 product
+    assert np.array_equal(gv, ref_gv), "grad_vals must be bitwise equal"
+    _check_grad_x(gx, A, g, store, False, f"ragged {store}")
+    # dot-product identity on the GPU results: <g, A x> = <A^T g, x>
+    from oracle import spmv as OS
+    lhs = np.dot(g, OS.spmv(A.row_ptr, A.col_idx, A.vals, x))
+    tol = (1e-12 if store == "f64" else 1e-5) * np.dot(np.abs(g), OS.spmv(A.row_ptr, A.col_idx, np.abs(A.vals),
+                                                                            np.abs(x)))
+    assert abs(lhs - np.dot(gx, x)) <= tol
+
+
+@pytest.mark.parametrize("nrhs", [2, 8])
+def test_adjoint_multi_rhs(nrhs):
+    A = random_sparse(3000, 7.0, seed=nrhs)
+    A.vals = A.vals.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(nrhs)
+    X = rng.uniform(-1, 1, (A.n, nrhs)).astype(np.float32).astype(np.float64)
+    G = rng.uniform(-1, 1, (A.n, nrhs)).astype(np.float32).astype(np.float64)
+    say("adjoint mrhs", nrhs)
+    M = _build(A, "f32", params(21, 4))
+    gx, gv = _adjoint(M, X, G)
+    _check_grad_x(gx, A, G, "f32", False, f"mrhs {nrhs}")
+    ref = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    scale = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+    beta = OP.gamma(nrhs, 2.0 ** -24)
+    assert np.all(np.abs(gv - ref) <= beta * scale)
+
+
+def test_adjoint_skips_outputs():
+    A = random_sparse(500, 4.0, seed=3)
+    M = _build(A, "f64", params(8, 2))
+    s = M.structure()
+    x = to_dev(np.random.default_rng(1).uniform(-1, 1, A.n), torch.float64)
+    g = to_dev(np.random.default_rng(2).uniform(-1, 1, A.n), torch.float64)
+    gx, gv = M.adjoint(x, g, grad_vals=False)
+    assert gv is None and gx is not None
+    gx2, gv2 = M.adjoint(x, g, grad_x=False)
+    torch.cuda.synchronize()
+    assert gx2 is None
+    ref = OA.grad_vals(s["row_ptr"], s["col_idx"], x.cpu().numpy(), g.cpu().numpy())
+    assert np.array_equal(gv2.cpu().numpy(), ref)
+
+
+def test_c4_full_adjoint_and_finite_differences():
+    w = workload_c4()
+    A, x, g = w["A"], w["x"], w["g"]
+    p = C.csrk_tune(A.n, A.nnz, "mi355x")
+    say("c4 adjoint", p)
+    M = _build(A, "f32", p)
+    gx, gv = _adjoint(M, x, g)
+    ref_gv = OA.grad_vals(A.row_ptr, A.col_idx, x, g).astype(np.float32).astype(np.float64)
+    assert np.array_equal(gv, ref_gv)
+    _check_grad_x(gx, A, g, "f32", False, "c4")
+    # central finite differences of L = <g, A x> on sampled coordinates; L is bilinear, so only the
+    # terms that touch the perturbed coordinate change: evaluate those exactly in FP64.
+    rng = np.random.default_rng(0)
+    rows = np.repeat(np.arange(A.n), np.diff(A.row_ptr.astype(np.int64)))
+    for j in rng.choice(A.n, 100, replace=False):
+        ks = np.nonzero(A.col_idx == j)[0]
+        h = 1e-3 * max(1.0, abs(x[j]))
+
+        def local(xj):
+            return np.sum(A.vals[ks] * g[rows[ks]] * xj)
+        fd = (local(x[j] + h) - local(x[j] - h)) / (2 * h)
+        scale = np.sum(np.abs(A.vals[ks] * g[rows[ks]]))
+        assert abs(fd - gx[j]) <= 1e-5 * scale + 1e-12
+    for k in rng.choice(A.nnz, 100, replace=False):
+        h = 1e-3 * max(1.0, abs(A.vals[k]))
+        fd = ((A.vals[k] + h) * g[rows[k]] * x[A.col_idx[k]] - (A.vals[k] - h) * g[rows[k]] * x[A.col_idx[k]]) / (2 * h)
+        assert abs(fd - gv[k]) <= 1e-6 * abs(g[rows[k]] * x[A.col_idx[k]]) + 1e-12
+
+
+def test_autograd_gradcheck_f64():
+    A = random_sparse(40, 4.0, seed=8, empty_row_frac=0.1)
+    M = _build(A, "f64", params(5, 2))
+    vals = M.values().clone().requires_grad_(True)
+    x = torch.randn(A.n, dtype=torch.float64, device="cuda", requires_grad=True)
+    assert torch.autograd.gradcheck(lambda v, xx: CsrkSpMV.apply(M, v, xx), (vals, x), eps=1e-6, atol=1e-9)
+
+
+def test_autograd_backward_matches_adjoint_f32():
+    A = random_sparse(1000, 5.0, seed=9)
+    M = _build(A, "f32", params(13, 3))
+    vals = M.values().clone().requires_grad_(True)
+    x = torch.rand(A.n, dtype=torch.float32, device="cuda").requires_grad_(True)
+    y = CsrkSpMV.apply(M, vals, x)
+    g = torch.rand_like(y)
+    y.backward(g)
+    gx, gv = M.adjoint(x.detach(), g, vals=vals.detach())
+    torch.cuda.synchronize()
+    assert torch.equal(vals.grad, gv)
+    assert torch.allclose(x.grad, gx, rtol=1e-5, atol=1e-6)

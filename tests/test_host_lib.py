@@ -1,0 +1,284 @@
+"""CPU tests of libcsrk.so: exports, the size model, bit-exact structure vs the oracle, error statuses.
+
+These call only host entry points (no GPU needed).
+"""
+
+import os
+
+import numpy as np
+import pytest
+
+from gen import laplacian, random_sparse, workload_c1, workload_c2
+from oracle import bandk as OB
+from oracle import stats as OS
+from oracle import tune as OT
+from paper_2203_05096_amd import _capi as C
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return C.lib()
+
+
+def test_exports_every_header_symbol(lib):
+    names = C.header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(C._SIGS), "binding and header disagree"
+
+
+def test_status_strings(lib):
+    for s in range(9):
+        assert C.csrk_status_string(s).startswith(C.STATUS[s])
+
+
+def _golden_vectors(golden_dir):
+    rows = []
+    with open(os.path.join(golden_dir, "paper_tune_vectors.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line and not line.startswith("alt"):
+                p = line.split()
+                rows.append((float(p[0]), *map(int, p[1:])))
+    return rows
+
+
+def test_tune_paper_vectors(golden_dir):
+    for r, case, vs, vr, as_, ar in _golden_vectors(golden_dir):
+        n = 10 ** 6
+        nnz = int(round(r * n))
+        v = C.csrk_tune(n, nnz, "volta")
+        a = C.csrk_tune(n, nnz, "ampere")
+        assert (v["ssrs"], v["srs"]) == (vs, vr), r
+        assert (a["ssrs"], a["srs"]) == (as_, ar), r
+
+
+def test_tune_matches_oracle_over_range():
+    rng = np.random.default_rng(0)
+    for _ in range(2000):
+        n = int(rng.integers(1, 10 ** 6))
+        nnz = int(rng.integers(1, 60 * n))
+        for model in ("volta", "ampere"):
+            p = C.csrk_tune(n, nnz, model)
+            assert (p["ssrs"], p["srs"]) == OT.paper_tune(n, nnz, model)[:2], (n, nnz, model)
+
+
+def test_tune_errors():
+    for n, nnz in ((0, 5), (5, 0), (-1, 3)):
+        with pytest.raises(C.CsrkError) as e:
+            C.csrk_tune(n, nnz, "volta")
+        assert e.value.name == "CSRK_ERR_ARG"
+    with pytest.raises(C.CsrkError):
+        C.csrk_tune(10, 10, 7)
+    p = C.csrk_tune(4096, 20224, "mi355x")
+    assert p["k"] == 3 and p["srs"] >= 1 and p["ssrs"] >= 1
+
+
+def _path(n):
+    rp, ci = [0], []
+    for i in range(n):
+        for j in (i - 1, i, i + 1):
+            if 0 <= j < n:
+                ci.append(j)
+        rp.append(len(ci))
+    return np.array(rp), np.array(ci)
+
+
+def _params(srs, ssrs, reorder="bandk"):
+    return {"k": 3, "srs": srs, "ssrs": ssrs, "lanes_per_row": 1, "waves_per_wg": 4, "reorder": reorder}
+
+
+def _lib_structure(row_ptr, col_idx, vals, srs, ssrs, reorder="bandk"):
+    h = C.csrk_build_host(row_ptr, col_idx, vals, _params(srs, ssrs, reorder))
+    try:
+        return C.csrk_copy_structure(h), C.csrk_get_info(h)
+    finally:
+        C.csrk_destroy(h)
+
+
+def _assert_same_as_oracle(A_rp, A_ci, A_vals, srs, ssrs, reorder="bandk"):
+    s, info = _lib_structure(A_rp, A_ci, A_vals, srs, ssrs, reorder)
+    if reorder == "bandk":
+        perm, sr_ptr, ssr_ptr = OB.bandk_v1(A_rp, A_ci, srs, ssrs)
+    elif reorder == "rcm":
+        perm, sr_ptr, ssr_ptr = OB.reorder_rcm(A_rp, A_ci, srs, ssrs)
+    else:
+        perm, sr_ptr, ssr_ptr = OB.reorder_none(len(A_rp) - 1, srs, ssrs)
+    rp2, ci2, v2, vmap = OB.apply_permutation(A_rp, A_ci, A_vals, perm)
+    assert np.array_equal(s["perm"], perm)
+    assert np.array_equal(s["sr_ptr"], sr_ptr)
+    assert np.array_equal(s["ssr_ptr"], ssr_ptr)
+    assert np.array_equal(s["row_ptr"], rp2)
+    assert np.array_equal(s["col_idx"], ci2)
+    assert np.array_equal(s["vals"].view(np.uint64), np.asarray(v2, dtype=np.float64).view(np.uint64))
+    assert np.array_equal(s["vmap"], vmap)
+    return s, info
+
+
+def test_worked_example_path12(golden_dir):
+    rp, ci = _path(12)
+    s, _ = _assert_same_as_oracle(rp, ci, np.arange(len(ci), dtype=np.float64), 2, 2)
+    assert s["perm"].tolist() == list(range(11, -1, -1))
+
+
+@pytest.mark.parametrize("seed,sym,srs,ssrs,empty", [(0, True, 4, 3, 0.1), (1, False, 8, 2, 0.0),
+                                                     (2, False, 3, 7, 0.3), (3, True, 1, 1, 0.0),
+                                                     (4, False, 16, 16, 0.05), (5, True, 5, 1, 0.2),
+                                                     (6, False, 64, 8, 0.0), (7, True, 2, 64, 0.5)])
+def test_bitexact_random(seed, sym, srs, ssrs, empty):
+    A = random_sparse(400, 4.0, seed=seed, empty_row_frac=empty, symmetric_pattern=sym)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, srs, ssrs)
+
+
+@pytest.mark.parametrize("reorder", ["rcm", "none"])
+def test_bitexact_other_orders(reorder):
+    A = random_sparse(300, 5.0, seed=9, empty_row_frac=0.1)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 6, 3, reorder)
+
+
+def test_bitexact_c1_and_stats():
+    A = workload_c1()["A"]
+    for srs, ssrs in ((8, 8), (64, 8), (15, 7), (7, 15)):
+        s, info = _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, srs, ssrs)
+    st = OS.row_stats(A.row_ptr)
+    assert info["n"] == A.n and info["nnz"] == A.nnz
+    assert abs(info["rdensity"] - st["r"]) < 1e-12 and abs(info["row_variance"] - st["var"]) < 1e-12
+    assert info["max_row"] == st["max"] and info["symmetry"] == 1.0
+    assert info["bandwidth"] == OB.bandwidth(s["row_ptr"], s["col_idx"])
+    assert info["bandwidth_input"] == 64 and info["on_device"] == 0
+
+
+def test_bitexact_medium_scrambled_3d():
+    w = workload_c2(seed=3, side=24)
+    A = w["A"]
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 14, 7)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 64, 8)
+
+
+def test_bitexact_nonsymmetric_drop():
+    from gen import stencil_pattern, drop_offdiagonals
+    rng = np.random.default_rng(4)
+    rp, ci, dg = stencil_pattern((48, 40), "2d9")
+    rp, ci, dg = drop_offdiagonals(rp, ci, dg, rng, 0.1)
+    vals = rng.uniform(-1, 1, len(ci))
+    _, info = _assert_same_as_oracle(rp, ci, vals, 18, 9)
+    assert abs(info["symmetry"] - OS.pattern_symmetry(rp, ci)) < 1e-12
+
+
+@pytest.mark.slow
+def test_bitexact_c2_full_size():
+    """The full 3D 7-point 128^3 scrambled workload: library vs oracle, bit for bit."""
+    w = workload_c2()
+    A = w["A"]
+    p = C.csrk_tune(A.n, A.nnz, "mi355x")
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, p["srs"], p["ssrs"])
+
+
+def test_from_groups_fig1(golden_dir):
+    # 9 rows, sizes of the paper's Fig. 1 example, identity ordering, tridiagonal pattern
+    rp, ci = _path(9)
+    h = C.csrk_build_from_groups(rp, ci, np.ones(len(ci)), np.arange(9), [2, 3, 2, 2], [2, 2], _params(1, 1))
+    s = C.csrk_copy_structure(h)
+    C.csrk_destroy(h)
+    assert s["sr_ptr"].tolist() == [0, 2, 5, 7, 9] and s["ssr_ptr"].tolist() == [0, 2, 4]
+
+
+def test_from_groups_errors():
+    rp, ci = _path(5)
+    bad = [([0, 1, 2, 3, 3], [2, 3], [2]), (np.arange(5), [2, 2], [2]), (np.arange(5), [2, 3], [1]),
+           (np.arange(5), [0, 5], [2])]
+    for perm, srz, ssrz in bad:
+        with pytest.raises(C.CsrkError) as e:
+            C.csrk_build_from_groups(rp, ci, None, perm, srz, ssrz, _params(1, 1))
+        assert e.value.name == "CSRK_ERR_ARG"
+
+
+def test_validation_statuses():
+    rp, ci = _path(6)
+    rp = np.asarray(rp)
+    ci = np.asarray(ci)
+    bad_start = rp.copy()
+    bad_start[0] = 1
+    decreasing = rp.copy()
+    decreasing[3] = decreasing[2] - 1
+    cases = [
+        (bad_start, ci, "CSRK_ERR_BAD_ROWPTR"),
+        (decreasing, ci, "CSRK_ERR_BAD_ROWPTR"),
+        (rp, np.r_[ci[:-1], 6], "CSRK_ERR_COL_RANGE"),
+        (rp, np.r_[ci[:-1], -1], "CSRK_ERR_COL_RANGE"),
+        (rp, np.r_[ci[:2], ci[1], ci[3:]], "CSRK_ERR_DUPLICATE"),
+    ]
+    for r, c, status in cases:
+        with pytest.raises(C.CsrkError) as e:
+            C.csrk_build_host(r, c, None, _params(2, 2))
+        assert e.value.name == status, (r, c)
+    # row_ptr[n] != nnz, through the raw entry point
+    import ctypes
+    r32 = np.ascontiguousarray(rp, np.int32)
+    c32 = np.ascontiguousarray(ci, np.int32)
+    h = ctypes.c_void_p()
+    st = C.lib().csrk_build_host(6, len(ci) + 1, r32.ctypes.data_as(C._i32p), c32.ctypes.data_as(C._i32p), None,
+                                 None, ctypes.byref(h))
+    assert C.STATUS[st] == "CSRK_ERR_BAD_ROWPTR"
+    st = C.lib().csrk_build_host(6, len(ci), None, c32.ctypes.data_as(C._i32p), None, None, ctypes.byref(h))
+    assert C.STATUS[st] == "CSRK_ERR_ARG"
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_build_host(rp, ci, None, _params(0, 2))
+    assert e.value.name == "CSRK_ERR_ARG"
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_build_host(rp, ci, None, dict(_params(2, 2), lanes_per_row=3))
+    assert e.value.name == "CSRK_ERR_ARG"
+    assert "lanes_per_row" in C.csrk_last_error_detail()
+
+
+def test_unsorted_columns_accepted():
+    rp, ci = _path(10)
+    ci2 = ci.copy()
+    for i in range(10):  # reverse each row
+        ci2[rp[i]:rp[i + 1]] = ci[rp[i]:rp[i + 1]][::-1]
+    vals = np.arange(len(ci), dtype=np.float64)
+    vals2 = vals.copy()
+    for i in range(10):
+        vals2[rp[i]:rp[i + 1]] = vals[rp[i]:rp[i + 1]][::-1]
+    a, _ = _lib_structure(rp, ci, vals, 3, 2)
+    b, _ = _lib_structure(rp, ci2, vals2, 3, 2)
+    for k in ("perm", "row_ptr", "col_idx", "vals", "sr_ptr", "ssr_ptr"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_empty_and_degenerate():
+    h = C.csrk_build_host(np.zeros(1, np.int32), np.zeros(0, np.int32), None, _params(4, 4))
+    info = C.csrk_get_info(h)
+    assert info["n"] == 0 and info["nsr"] == 0 and info["nssr"] == 0
+    C.csrk_destroy(h)
+    # a single row without entries
+    h = C.csrk_build_host(np.zeros(2, np.int32), np.zeros(0, np.int32), None, _params(4, 4))
+    s = C.csrk_copy_structure(h)
+    assert s["sr_ptr"].tolist() == [0, 1] and s["ssr_ptr"].tolist() == [0, 1]
+    C.csrk_destroy(h)
+    # diagonal matrix: no graph edges
+    n = 33
+    _assert_same_as_oracle(np.arange(n + 1), np.arange(n), np.linspace(1, 2, n), 4, 3)
+
+
+def test_device_calls_need_device_arrays():
+    rp, ci = _path(8)
+    h = C.csrk_build_host(rp, ci, np.ones(len(ci)), _params(2, 2))
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_spmv(h, None, 1 << 20, 2 << 20, 1, None)
+    assert e.value.name == "CSRK_ERR_UNSUPPORTED"
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_device_vals(h)
+    assert e.value.name == "CSRK_ERR_UNSUPPORTED"
+    C.csrk_destroy(h)
+
+
+def test_upload_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rp, ci = _path(8)
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_build(rp, ci, np.ones(len(ci)), _params(2, 2), "f64")
+    assert e.value.name == "CSRK_ERR_DEVICE"
