@@ -178,16 +178,37 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        flush_buf = torch.empty(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        flush_buf = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
 
         def flush():
-            flush_buf.zero_()
+            # a read-only pass over 1 GiB evicts the L2s and the 256 MB Infinity Cache without leaving
+            # dirty lines behind for the timed kernel to write back
+            flush_buf.sum()
 
         fm, fmin = flushed_ms(torch, fwd, flush)
         am, amin = flushed_ms(torch, adj, flush)
         extras["flushed"] = {"forward_us": round(fm * 1e3, 2), "forward_GBs": round(fb / (fm * 1e-3) / 1e9, 1),
                              "adjoint_us": round(am * 1e3, 2), "adjoint_GBs": round(ab / (am * 1e-3) / 1e9, 1),
-                             "note": "L2 and Infinity Cache flushed (1 GiB write) before each launch, 20 runs"}
+                             "note": "L2 and Infinity Cache flushed (1 GiB read) before each launch, 20 runs"}
+
+        def adj_gx_only():
+            if lib.csrk_spmv_adjoint(h, None, px, pg, pgx, None, 1, stream):
+                raise RuntimeError(C.csrk_last_error_detail())
+
+        def adj_gv_only():
+            if lib.csrk_spmv_adjoint(h, None, px, pg, None, pgv, 1, stream):
+                raise RuntimeError(C.csrk_last_error_detail())
+
+        _, (gxm, gvm) = timed_launches(torch, [adj_gx_only, adj_gv_only], 50, 5)
+        extras["adjoint_parts"] = {"grad_x_only_us": round(gxm * 1e3, 2), "grad_vals_only_us": round(gvm * 1e3, 2)}
+        # attainable HBM bandwidth on this machine: a streaming read (reduction) and a copy of 2 GiB
+        big = torch.ones(1 << 28, dtype=torch.float64, device="cuda")
+        big2 = torch.empty_like(big)
+        _, (rd, cp) = timed_launches(torch, [lambda: big.sum(), lambda: big2.copy_(big)], 10, 2)
+        extras["hbm_calibration"] = {"read_GBs": round(big.numel() * 8 / (rd * 1e-3) / 1e9, 1),
+                                     "copy_GBs": round(2 * big.numel() * 8 / (cp * 1e-3) / 1e9, 1),
+                                     "note": "torch sum / copy_ of a 2 GiB float64 tensor, event-timed"}
+        del big, big2
         plain = {}
         for name, reorder in (("input_order", "none"), ("rcm", "rcm"), ("bandk", None)):
             if reorder is None:

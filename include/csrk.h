@@ -23,9 +23,10 @@
  *    as void* (NULL = the default stream).  Device calls are enqueued
  *    asynchronously on that stream and never synchronise implicitly.
  *  - Blocks of right-hand sides are row-major n x nrhs.
- *  - A handle is immutable after it is built; concurrent device calls on one
- *    handle from different streams are safe.  csrk_destroy must not overlap
- *    calls still in flight (synchronise the stream first).
+ *  - A handle's structure is immutable after it is built; concurrent device
+ *    calls on one handle from different streams are safe.  csrk_set_launch
+ *    and csrk_destroy must not overlap calls still in flight (synchronise the
+ *    stream first).
  */
 #ifndef CSRK_H
 #define CSRK_H
@@ -149,6 +150,15 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store);
 /* csrk_build = csrk_build_host followed by csrk_upload. */
 csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
                        const csrk_params *p, csrk_dtype store, csrk_handle *out);
+
+/*
+ * csrk_set_launch — change the kernel launch shape of a built handle
+ * (lanes_per_row: 1, 2, 4, ..., 64; waves_per_wg: 1..16) without rebuilding
+ * its structure: the shape does not affect the ordering or grouping.  Used by
+ * the autotuner.  Must not overlap device calls on the same handle.
+ * Errors: CSRK_ERR_ARG.
+ */
+csrk_status csrk_set_launch(csrk_handle h, int32_t lanes_per_row, int32_t waves_per_wg);
 
 /* Statistics and parameters of a handle. */
 csrk_status csrk_get_info(csrk_handle h, csrk_info *out);

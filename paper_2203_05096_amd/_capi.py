@@ -70,6 +70,7 @@ _SIGS = {
     "csrk_upload": ([_h, ctypes.c_int], ctypes.c_int),
     "csrk_build": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params), ctypes.c_int,
                     ctypes.POINTER(_h)], ctypes.c_int),
+    "csrk_set_launch": ([_h, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "csrk_get_info": ([_h, ctypes.POINTER(csrk_info)], ctypes.c_int),
     "csrk_copy_structure": ([_h, _i32p, _i32p, _i32p, _f64p, _i64p, _i32p, _i32p], ctypes.c_int),
     "csrk_device_vals": ([_h, ctypes.POINTER(_vp)], ctypes.c_int),
@@ -194,6 +195,10 @@ def csrk_build(row_ptr, col_idx, vals, params=None, store: str = "f64") -> int:
     _check(lib().csrk_build(len(rp) - 1, int(rp[-1]), _ptr(rp, _i32p), _ptr(ci, _i32p), _ptr(va, _f64p),
                             ctypes.byref(p) if p is not None else None, DTYPES[store], ctypes.byref(h)), "csrk_build")
     return h.value
+
+
+def csrk_set_launch(h: int, lanes_per_row: int, waves_per_wg: int):
+    _check(lib().csrk_set_launch(h, int(lanes_per_row), int(waves_per_wg)), "csrk_set_launch")
 
 
 def csrk_get_info(h: int) -> dict:

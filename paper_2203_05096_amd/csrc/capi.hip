@@ -25,12 +25,15 @@ struct csrk_matrix {
     std::vector<double> vals;
     csrk::Stats in_stats, out_stats;
     int32_t max_sr_nnz = 0, max_ssr_rows = 0;
+    csrk::Transposed trans;  // index structure of A'^T for the adjoint
     // device side
     bool on_device = false;
     csrk_dtype store = CSRK_F64;
     int device = -1;
     int32_t *d_row_ptr = nullptr, *d_col_idx = nullptr, *d_sr_ptr = nullptr, *d_ssr_ptr = nullptr, *d_perm = nullptr;
+    int32_t *d_t_row_ptr = nullptr, *d_t_col = nullptr, *d_t_src = nullptr;  // t_row_ptr/t_col only if nonsymmetric
     void *d_vals = nullptr;
+    void *d_vals_t = nullptr;  // stored values in A'^T order, for the adjoint
 };
 
 struct csrk_batch_s {
@@ -96,10 +99,12 @@ void free_device(csrk_matrix *h) {
     if (!h->on_device) return;
     DeviceScope ds(h->device);
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
-                    (void *)h->d_perm, h->d_vals})
+                    (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
+                    h->d_vals_t})
         if (p) (void)hipFree(p);
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
-    h->d_vals = nullptr;
+    h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
+    h->d_vals = h->d_vals_t = nullptr;
     h->on_device = false;
 }
 
@@ -135,6 +140,7 @@ void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx,
     h->max_ssr_rows = 0;
     for (size_t t = 0; t + 1 < h->ssr_ptr.size(); ++t)
         h->max_ssr_rows = std::max(h->max_ssr_rows, h->sr_ptr[h->ssr_ptr[t + 1]] - h->sr_ptr[h->ssr_ptr[t]]);
+    h->trans = csrk::transpose_index(h->n, h->row_ptr, h->col_idx);
 }
 
 csrk_params resolve_params(int32_t n, int64_t nnz, const csrk_params *p) {
@@ -163,6 +169,12 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.sr_ptr = h->d_sr_ptr;
     a.ssr_ptr = h->d_ssr_ptr;
     a.perm = h->d_perm;
+    const bool sym = h->trans.symmetric;
+    a.t_row_ptr = sym ? h->d_row_ptr : h->d_t_row_ptr;
+    a.t_col = sym ? h->d_col_idx : h->d_t_col;
+    a.t_src = h->d_t_src;
+    a.vals_t = h->d_vals_t;
+    a.sym = sym;
     return a;
 }
 
@@ -173,6 +185,10 @@ void need_device(const csrk_matrix *h) {
 
 void check_vec(const void *p, const csrk_matrix *h, const char *name) {
     if (h->n > 0 && !p) throw Error{CSRK_ERR_ARG, std::string(name) + " is NULL"};
+}
+
+void check_align16(const void *p, const char *name) {
+    if (reinterpret_cast<uintptr_t>(p) % 16 != 0) throw Error{CSRK_ERR_ARG, std::string(name) + " must be 16-byte aligned"};
 }
 
 const void *values_for(const csrk_matrix *h, const void *vals_dev) {
@@ -300,11 +316,18 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
             h->d_sr_ptr = upload_array(h->sr_ptr, "sr_ptr");
             h->d_ssr_ptr = upload_array(h->ssr_ptr, "ssr_ptr");
             h->d_perm = upload_array(h->perm, "perm");
+            h->d_t_src = upload_array(h->trans.t_src, "transposed map");
+            if (!h->trans.symmetric) {
+                h->d_t_row_ptr = upload_array(h->trans.t_row_ptr, "transposed row_ptr");
+                h->d_t_col = upload_array(h->trans.t_col, "transposed col_idx");
+            }
             hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
+            hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
             h->on_device = true;
             if (h->nnz > 0) {
                 double *tmp = upload_array(h->vals, "vals (staging)");
                 hipError_t e = csrk::dev::convert_values(tmp, h->d_vals, h->nnz, store, nullptr);
+                if (e == hipSuccess) e = csrk::dev::transpose_values(arrays_of(h), store, h->d_vals, h->d_vals_t, nullptr);
                 hipError_t e2 = hipDeviceSynchronize();
                 (void)hipFree(tmp);
                 hip_check(e, "value conversion");
@@ -331,6 +354,18 @@ csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int
         g_detail = keep;
     }
     return s;
+}
+
+csrk_status csrk_set_launch(csrk_handle h, int32_t lanes_per_row, int32_t waves_per_wg) {
+    return guard([&] {
+        if (!h) throw Error{CSRK_ERR_ARG, "null handle"};
+        csrk_params q = h->params;
+        q.lanes_per_row = lanes_per_row;
+        q.waves_per_wg = waves_per_wg;
+        csrk::check_params(q);
+        h->params = q;
+        return CSRK_OK;
+    });
 }
 
 csrk_status csrk_get_info(csrk_handle h, csrk_info *out) {
@@ -428,9 +463,10 @@ csrk_status csrk_spmv_adjoint(csrk_handle h, const void *vals_dev, const void *x
         if (!grad_x_dev && !grad_vals_dev) return CSRK_OK;
         if (grad_x_dev && h->n > 0 && (grad_x_dev == g_dev || grad_x_dev == x_dev))
             throw Error{CSRK_ERR_ARG, "grad_x must not alias x or g"};
-        const void *v = values_for(h, vals_dev);
+        if (grad_vals_dev) check_align16(grad_vals_dev, "grad_vals");
+        if (vals_dev) check_align16(vals_dev, "vals_dev");
         DeviceScope ds(h->device);
-        hip_check(csrk::dev::adjoint(arrays_of(h), h->store, v, x_dev, g_dev, grad_x_dev, grad_vals_dev, nrhs,
+        hip_check(csrk::dev::adjoint(arrays_of(h), h->store, vals_dev, x_dev, g_dev, grad_x_dev, grad_vals_dev, nrhs,
                                      shape_of(h), static_cast<hipStream_t>(stream)),
                   "csrk_spmv_adjoint launch");
         return CSRK_OK;
@@ -522,6 +558,10 @@ csrk::dev::MatDesc *upload_descs(csrk_batch b, int which, const void *const *val
         m.sr_ptr = h->d_sr_ptr;
         m.row_ptr = h->d_row_ptr;
         m.col_idx = h->d_col_idx;
+        const csrk::dev::Arrays a = arrays_of(h);
+        m.t_row_ptr = a.t_row_ptr;
+        m.t_col = a.t_col;
+        m.t_src = a.t_src;
         m.vals = values_for(h, vals ? vals[i] : nullptr);
         m.x = x ? x[i] : nullptr;
         m.y = y ? y[i] : nullptr;
@@ -531,6 +571,13 @@ csrk::dev::MatDesc *upload_descs(csrk_batch b, int which, const void *const *val
         m.nnz = h->nnz;
         m.n = h->n;
         m.nssr = static_cast<int32_t>(h->ssr_ptr.size()) - 1;
+        m.sym = h->trans.symmetric ? 1 : 0;
+        if (which == 1) {
+            // adjoint: caller values (CSR-k order, reached through t_src) when any
+            // are given, otherwise the handles' transposed copies
+            const bool any = vals && std::any_of(vals, vals + count, [](const void *p) { return p != nullptr; });
+            m.vals = any ? values_for(h, vals[i]) : h->d_vals_t;
+        }
     }
     if (b->last_valid[which] && std::memcmp(d.data(), b->last[which].data(), count * sizeof(d[0])) == 0)
         return b->d_descs[which];
@@ -579,13 +626,14 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         for (size_t i = 0; i < b->handles.size(); ++i) {
             check_vec(g[i], b->handles[i], "g");
             if (grad_vals) check_vec(x ? x[i] : nullptr, b->handles[i], "x");
+            if (grad_vals && grad_vals[i]) check_align16(grad_vals[i], "grad_vals");
         }
         DeviceScope ds(b->device);
         hipStream_t st = static_cast<hipStream_t>(stream);
         csrk::dev::MatDesc *descs = upload_descs(b, 1, vals, x, nullptr, g, grad_x, grad_vals, st);
-        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems,
-                                           static_cast<int32_t>(b->handles.size()), b->max_n, b->store, nrhs,
-                                           b->shape, batch_grid(b, nrhs, true), st),
+        const bool ind = vals && std::any_of(vals, vals + b->handles.size(), [](const void *p) { return p != nullptr; });
+        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
+                                           batch_grid(b, nrhs, true), ind, st),
                   "csrk_batch_spmv_adjoint launch");
         return CSRK_OK;
     });

@@ -83,53 +83,70 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
-// V consecutive values / column indices starting at pos (pos % V == 0); the
-// tail beyond nnz (array end) is read element by element.
-template <typename VT>
-__device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int32_t *__restrict__ cols, int64_t pos,
-                                         int64_t nnz, typename Store<VT>::A (&v)[Store<VT>::V],
-                                         int32_t (&c)[Store<VT>::V]) {
+// V consecutive column indices starting at pos (pos % V == 0) and the values
+// of those entries: vals[pos + e], or vals[src[pos + e]] when the values are
+// reached through an index map (IND).  Entries at or beyond nnz read as 0.
+template <typename VT, bool IND>
+__device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int32_t *__restrict__ cols,
+                                         const int32_t *__restrict__ src, int64_t pos, int64_t nnz,
+                                         typename Store<VT>::A (&v)[Store<VT>::V], int32_t (&c)[Store<VT>::V]) {
     constexpr int V = Store<VT>::V;
+    typedef int32_t CV __attribute__((ext_vector_type(V)));
     if (pos + V <= nnz) {
-        typedef VT VV __attribute__((ext_vector_type(V)));
-        typedef int32_t CV __attribute__((ext_vector_type(V)));
-        const VV vv = *reinterpret_cast<const VV *>(vals + pos);
         const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+        if constexpr (IND) {
+            const CV sv = *reinterpret_cast<const CV *>(src + pos);
 #pragma unroll
-        for (int e = 0; e < V; ++e) {
-            v[e] = Store<VT>::widen(vv[e]);
-            c[e] = cv[e];
+            for (int e = 0; e < V; ++e) {
+                c[e] = cv[e];
+                v[e] = Store<VT>::widen(vals[sv[e]]);
+            }
+        } else {
+            typedef VT VV __attribute__((ext_vector_type(V)));
+            const VV vv = *reinterpret_cast<const VV *>(vals + pos);
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                c[e] = cv[e];
+                v[e] = Store<VT>::widen(vv[e]);
+            }
         }
     } else {
 #pragma unroll
         for (int e = 0; e < V; ++e) {
             const bool ok = pos + e < nnz;
-            v[e] = ok ? Store<VT>::widen(vals[pos + e]) : typename Store<VT>::A(0);
             c[e] = ok ? cols[pos + e] : 0;
+            v[e] = ok ? Store<VT>::widen(vals[IND ? src[pos + e] : pos + e]) : typename Store<VT>::A(0);
         }
     }
 }
 
 // ------------------------------------------------------------------ forward
 
-// y[r0..r1) for one super-row, single right-hand side.
-template <typename VT, int L>
+// y[r0..r1) = rows r0..r1-1 of (values) * x, one super-row, single right-hand
+// side.  The wavefront walks the super-row in windows of at most 64 whole
+// rows whose nonzeros fit its LDS staging area.  Per window: every lane issues
+// all its 16-byte loads of col_idx / values for the whole window before the
+// dependent x gathers; the row ends of the next window are fetched meanwhile;
+// products go to LDS and each row is then summed by L lanes.
+template <typename VT, int L, bool IND>
 __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
-                                           const int32_t *__restrict__ cols, const VT *__restrict__ vals,
-                                           const typename Store<VT>::X *__restrict__ x,
+                                           const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                           const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                            typename Store<VT>::X *__restrict__ y, int64_t nnz,
                                            typename Store<VT>::A *__restrict__ buf, int lane) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
     constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int U = CAP / (kWave * V);  // unrolled stream steps covering CAP entries
+    constexpr int WIN = CAP - V;          // window limit: an unaligned window still fits U steps
+    static_assert(U >= 1 && U * kWave * V == CAP, "staging area must be a whole number of steps");
     int32_t ra = r0;
     int32_t cs = uniform(row_ptr[r0]);
+    int32_t my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
     while (ra < r1) {
-        const int32_t my_row = ra + lane;
-        const bool in = my_row < r1;
-        const int32_t my_end = in ? row_ptr[my_row + 1] : 0;
-        const bool fits = in && (my_end - cs <= CAP);
+        const bool in = ra + lane < r1;
+        const bool fits = in && (my_end - cs <= WIN);
         const uint64_t mask = __ballot(fits);
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
@@ -137,28 +154,52 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
             const int32_t re = uniform(__shfl(my_end, 0));
             A acc = 0;
             for (int64_t k = int64_t(cs) + lane; k < re; k += kWave)
-                acc += Store<VT>::widen(vals[k]) * A(x[cols[k]]);
+                acc += Store<VT>::widen(vals[IND ? src[k] : k]) * A(x[cols[k]]);
             acc = group_sum<kWave>(acc);
             if (lane == 0) y[ra] = X(acc);
             cs = re;
             ++ra;
+            my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
             continue;
         }
         const int32_t ce = uniform(__shfl(my_end, nrows - 1));
-        for (int64_t pos = int64_t(cs & ~(V - 1)) + int64_t(lane) * V; pos < ce; pos += int64_t(kWave) * V) {
-            A v[V];
-            int32_t c[V];
-            load_vec<VT>(vals, cols, pos, nnz, v, c);
+        const int32_t nra = ra + nrows;
+        const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
+        const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+        A v[U][V];
+        int32_t c[U][V];
 #pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int64_t k = pos + e;
-                if (k >= cs && k < ce) buf[k - cs] = v[e] * A(x[c[e]]);
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < ce) {
+                load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
             }
         }
+        A xv[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                xv[u][e] = (k >= cs && k < ce) ? A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                if (k >= cs && k < ce) buf[k - cs] = v[u][e] * xv[u][e];
+            }
         wave_lds_sync();
 #pragma unroll 1
-        for (int base = 0; base < nrows; base += kWave / L) {
-            const int rr = base + lane / L;
+        for (int b = 0; b < nrows; b += kWave / L) {
+            const int rr = b + lane / L;
             const bool act = rr < nrows;
             const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
             const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
@@ -171,7 +212,8 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
         }
         wave_lds_sync();
         cs = ce;
-        ra += nrows;
+        ra = nra;
+        my_end = next_end;
     }
 }
 
@@ -190,14 +232,17 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward<VT, L>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, vals, x, y, nnz, buf, lane);
+        sr_forward<VT, L, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y, nnz,
+                                 buf, lane);
 }
 
 // y for one super-row, nrhs right-hand sides (row-major): R lanes per row cover
-// R consecutive columns of the block; 64/R rows per pass.
-template <typename VT, int R>
+// R consecutive columns of the block; 64/R rows per pass.  Values are vals[k]
+// or vals[src[k]] (IND).
+template <typename VT, int R, bool IND>
 __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
-                                                const int32_t *__restrict__ cols, const VT *__restrict__ vals,
+                                                const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                                const VT *__restrict__ vals,
                                                 const typename Store<VT>::X *__restrict__ x,
                                                 typename Store<VT>::X *__restrict__ y, int nrhs, int lane) {
     using A = typename Store<VT>::A;
@@ -214,7 +259,7 @@ __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const in
                 const int32_t kb = row_ptr[row], ke = row_ptr[row + 1];
 #pragma unroll 4
                 for (int32_t k = kb; k < ke; ++k)
-                    acc += Store<VT>::widen(vals[k]) * A(x[int64_t(cols[k]) * nrhs + col]);
+                    acc += Store<VT>::widen(vals[IND ? src[k] : k]) * A(x[int64_t(cols[k]) * nrhs + col]);
                 y[int64_t(row) * nrhs + col] = X(acc);
             }
         }
@@ -234,46 +279,106 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
     const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward_mrhs<VT, R>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, vals, x, y, nrhs, lane);
+        sr_forward_mrhs<VT, R, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y,
+                                      nrhs, lane);
 }
 
 // ------------------------------------------------------------------ adjoint
+//
+// No atomics: both gradients are row-local.
+//   grad_vals[k] = g_i x_j for the entries k of rows i of the super-row
+//     (a pure stream: coalesced col_idx loads and grad_vals stores);
+//   grad_x[j] = sum over column j of A' of a_ij g_i = row j of A'^T times g,
+//     computed like the forward product over the transposed index structure
+//     (t_row_ptr, t_col) with each value fetched through t_src.
+// Both use the rows of the same super-row, so the SSR -> workgroup and
+// SR -> wavefront mapping carries over unchanged.
 
-// grad_x += A^T g (atomics) and grad_vals = g_i x_j for one super-row.
-// L lanes per row stride over the row's nonzeros; R lanes cover RHS columns.
-template <typename VT, int L>
-__device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
-                                           const int32_t *__restrict__ cols, const VT *__restrict__ vals,
-                                           const typename Store<VT>::X *__restrict__ x,
-                                           const typename Store<VT>::X *__restrict__ g,
-                                           typename Store<VT>::X *__restrict__ gx, typename Store<VT>::A *__restrict__ gv,
-                                           int lane) {
+// grad_vals for rows r0..r1-1, single right-hand side.  Each window's rows
+// write their local index over their entries in an LDS byte map, so the stream
+// can find g_i for any entry.
+template <typename VT>
+__device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
+                                             const int32_t *__restrict__ cols,
+                                             const typename Store<VT>::X *__restrict__ x,
+                                             const typename Store<VT>::X *__restrict__ g,
+                                             typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                             unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
-    using X = typename Store<VT>::X;
-    const int sub = lane % L;
-    for (int32_t rb = r0; rb < r1; rb += kWave / L) {
-        const int32_t row = rb + lane / L;
-        if (row < r1) {
-            const A gi = A(g[row]);
-            const int32_t ke = row_ptr[row + 1];
-            for (int32_t k = row_ptr[row] + sub; k < ke; k += L) {
-                const int32_t j = cols[k];
-                if (gv) gv[k] = gi * A(x[j]);
-                if (gx) unsafeAtomicAdd(&gx[j], X(Store<VT>::widen(vals[k]) * gi));
+    constexpr int VA = 16 / int(sizeof(A));  // grad_vals entries per 16-byte store
+    constexpr int MAPB = kStageBytes - kWave * int(sizeof(A));
+    constexpr int WIN = MAPB - VA;
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    typedef int32_t CV __attribute__((ext_vector_type(VA)));
+    unsigned char *rowid = lds;
+    A *gwin = reinterpret_cast<A *>(lds + MAPB);
+    int32_t ra = r0;
+    int32_t cs = uniform(row_ptr[r0]);
+    while (ra < r1) {
+        const bool in = ra + lane < r1;
+        const int32_t my_end = in ? row_ptr[ra + lane + 1] : 0;
+        const bool fits = in && (my_end - cs <= WIN);
+        const uint64_t mask = __ballot(fits);
+        const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
+        if (nrows == 0) {
+            const int32_t re = uniform(__shfl(my_end, 0));
+            const A gi = A(g[ra]);
+            for (int64_t k = int64_t(cs) + lane; k < re; k += kWave) gv[k] = gi * A(x[cols[k]]);
+            cs = re;
+            ++ra;
+            continue;
+        }
+        const int32_t ce = uniform(__shfl(my_end, nrows - 1));
+        const int32_t prev_end = __shfl(my_end, lane > 0 ? lane - 1 : 0);
+        if (lane < nrows) {
+            gwin[lane] = A(g[ra + lane]);
+            for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
+        }
+        wave_lds_sync();
+        for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ce; pos += int64_t(kWave) * VA) {
+            int32_t c[VA];
+            if (pos + VA <= nnz) {
+                const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[e] = cv[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[e] = pos + e < nnz ? cols[pos + e] : 0;
+            }
+            A out[VA];
+#pragma unroll
+            for (int e = 0; e < VA; ++e) {
+                const int64_t k = pos + e;
+                out[e] = (k >= cs && k < ce) ? gwin[rowid[k - cs]] * A(x[c[e]]) : A(0);
+            }
+            if (pos >= cs && pos + VA <= ce) {
+                AV ov;
+#pragma unroll
+                for (int e = 0; e < VA; ++e) ov[e] = out[e];
+                *reinterpret_cast<AV *>(gv + pos) = ov;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) {
+                    const int64_t k = pos + e;
+                    if (k >= cs && k < ce) gv[k] = out[e];
+                }
             }
         }
+        wave_lds_sync();
+        cs = ce;
+        ra += nrows;
     }
 }
 
+// grad_vals for several right-hand sides: R lanes per row cover R columns of
+// the block and reduce sum_c g[i,c] x[j,c] per entry with wavefront shuffles.
 template <typename VT, int R>
-__device__ __forceinline__ void sr_adjoint_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
-                                                const int32_t *__restrict__ cols, const VT *__restrict__ vals,
-                                                const typename Store<VT>::X *__restrict__ x,
-                                                const typename Store<VT>::X *__restrict__ g,
-                                                typename Store<VT>::X *__restrict__ gx,
-                                                typename Store<VT>::A *__restrict__ gv, int nrhs, int lane) {
+__device__ __forceinline__ void sr_grad_vals_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ cols,
+                                                  const typename Store<VT>::X *__restrict__ x,
+                                                  const typename Store<VT>::X *__restrict__ g,
+                                                  typename Store<VT>::A *__restrict__ gv, int nrhs, int lane) {
     using A = typename Store<VT>::A;
-    using X = typename Store<VT>::X;
     const int c = lane % R;
     const int rr = lane / R;
     for (int cb = 0; cb < nrhs; cb += R) {
@@ -286,36 +391,191 @@ __device__ __forceinline__ void sr_adjoint_mrhs(int32_t r0, int32_t r1, const in
                 const int32_t ke = row_ptr[row + 1];
                 for (int32_t k = row_ptr[row]; k < ke; ++k) {
                     const int64_t j = cols[k];
-                    if (gx && cok) unsafeAtomicAdd(&gx[j * nrhs + col], X(Store<VT>::widen(vals[k]) * gi));
                     A p = cok ? gi * A(x[j * nrhs + col]) : A(0);
                     p = group_sum<R>(p);
-                    if (gv && c == 0) gv[k] = cb == 0 ? p : gv[k] + p;
+                    if (c == 0) gv[k] = cb == 0 ? p : gv[k] + p;
                 }
             }
         }
     }
 }
 
-template <typename VT, int L>
+// Both gradients of one super-row, symmetric pattern, single right-hand side,
+// in one pass: row i of A'^T has the pattern of row i of A', so the same
+// stream of col_idx serves grad_vals[k] = g_i x_j and the products
+// a_ji g_j of grad_x[i].  Transposed values come from valsT[k] (the handle's
+// stored transposed copy) or vals[src[k]] (IND: values passed by the caller).
+// LDS per wavefront: products (kStageBytes) | row map (CAP bytes) | g of the
+// window's rows (64 entries).
+template <typename VT, int L, bool IND>
+__device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                                 const VT *__restrict__ valsT,
+                                                 const typename Store<VT>::X *__restrict__ x,
+                                                 const typename Store<VT>::X *__restrict__ g,
+                                                 typename Store<VT>::X *__restrict__ gx,
+                                                 typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                 unsigned char *__restrict__ lds, int lane) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int U = CAP / (kWave * V);
+    constexpr int WIN = CAP - V;
+    typedef A AV __attribute__((ext_vector_type(V)));
+    A *buf = reinterpret_cast<A *>(lds);
+    unsigned char *rowid = lds + kStageBytes;
+    A *gwin = reinterpret_cast<A *>(lds + kStageBytes + CAP);
+    int32_t ra = r0;
+    int32_t cs = uniform(row_ptr[r0]);
+    int32_t my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+    while (ra < r1) {
+        const bool in = ra + lane < r1;
+        const bool fits = in && (my_end - cs <= WIN);
+        const uint64_t mask = __ballot(fits);
+        const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
+        if (nrows == 0) {
+            // Row ra alone exceeds the staging window: both gradients straight from memory.
+            const int32_t re = uniform(__shfl(my_end, 0));
+            const A gi = A(g[ra]);
+            A acc = 0;
+            for (int64_t k = int64_t(cs) + lane; k < re; k += kWave) {
+                const int32_t j = cols[k];
+                gv[k] = gi * A(x[j]);
+                acc += Store<VT>::widen(valsT[IND ? src[k] : k]) * A(g[j]);
+            }
+            acc = group_sum<kWave>(acc);
+            if (lane == 0) gx[ra] = X(acc);
+            cs = re;
+            ++ra;
+            my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+            continue;
+        }
+        const int32_t ce = uniform(__shfl(my_end, nrows - 1));
+        const int32_t nra = ra + nrows;
+        const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
+        const int32_t prev_end = __shfl(my_end, lane > 0 ? lane - 1 : 0);
+        const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+        A v[U][V];
+        int32_t c[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < ce) {
+                load_vec<VT, IND>(valsT, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
+            }
+        }
+        if (lane < nrows) {
+            gwin[lane] = A(g[ra + lane]);
+            for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
+        }
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            A gvv[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = pos + e;
+                const bool ok = k >= cs && k < ce;
+                const A xj = ok ? A(x[c[u][e]]) : A(0);
+                const A gj = ok ? A(g[c[u][e]]) : A(0);
+                gvv[e] = ok ? gwin[rowid[k - cs]] * xj : A(0);
+                if (ok) buf[k - cs] = v[u][e] * gj;
+            }
+            if (pos >= cs && pos + V <= ce) {
+                AV ov;
+#pragma unroll
+                for (int e = 0; e < V; ++e) ov[e] = gvv[e];
+                *reinterpret_cast<AV *>(gv + pos) = ov;
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int64_t k = pos + e;
+                    if (k >= cs && k < ce) gv[k] = gvv[e];
+                }
+            }
+        }
+        wave_lds_sync();
+#pragma unroll 1
+        for (int b = 0; b < nrows; b += kWave / L) {
+            const int rr = b + lane / L;
+            const bool act = rr < nrows;
+            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+            const int32_t rbeg = rr == 0 ? 0 : prev;
+            A acc = 0;
+            if (act)
+                for (int32_t k = rbeg + (lane % L); k < rend; k += L) acc += buf[k];
+            acc = group_sum<L>(acc);
+            if (act && (lane % L) == 0) gx[ra + rr] = X(acc);
+        }
+        wave_lds_sync();
+        cs = ce;
+        ra = nra;
+        my_end = next_end;
+    }
+}
+
+// Both gradients of one super-row.  `valsT` holds the transposed values
+// (aligned with t_col) unless IND, in which case it holds the caller's values
+// in CSR-k order and each transposed value is vals[t_src[p]].
+template <typename VT, int L, bool IND>
+__device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
+                                           const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr,
+                                           const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src,
+                                           const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
+                                           const typename Store<VT>::X *__restrict__ g,
+                                           typename Store<VT>::X *__restrict__ gx,
+                                           typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, bool sym,
+                                           unsigned char *__restrict__ lds, int lane) {
+    using A = typename Store<VT>::A;
+    if (nrhs == 1) {
+        if (sym && gx && gv) {
+            sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane);
+            return;
+        }
+        if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane);
+        if (gx)
+            sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, reinterpret_cast<A *>(lds),
+                                   lane);
+    } else {
+        if (gv) sr_grad_vals_mrhs<VT, L>(r0, r1, row_ptr, cols, x, g, gv, nrhs, lane);
+        if (gx) sr_forward_mrhs<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nrhs, lane);
+    }
+}
+
+// LDS bytes per wavefront of the adjoint kernels.
+constexpr int kAdjointLds = kStageBytes + 1024 + 64 * 8;
+
+template <typename VT, int L, bool IND>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                        const int32_t *__restrict__ row_ptr,
-                                                       const int32_t *__restrict__ cols, const VT *__restrict__ vals,
+                                                       const int32_t *__restrict__ cols,
+                                                       const int32_t *__restrict__ t_row_ptr,
+                                                       const int32_t *__restrict__ t_col,
+                                                       const int32_t *__restrict__ t_src, const VT *__restrict__ valsT,
                                                        const typename Store<VT>::X *__restrict__ x,
                                                        const typename Store<VT>::X *__restrict__ g,
                                                        typename Store<VT>::X *__restrict__ gx,
-                                                       typename Store<VT>::A *__restrict__ gv, int nrhs) {
+                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
+                                                       int sym) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    unsigned char *lds = smem + size_t(wave) * kAdjointLds;
     const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-    for (int32_t s = s0 + wave; s < s1; s += nw) {
-        const int32_t r0 = uniform(sr_ptr[s]), r1 = uniform(sr_ptr[s + 1]);
-        if (nrhs == 1)
-            sr_adjoint<VT, L>(r0, r1, row_ptr, cols, vals, x, g, gx, gv, lane);
-        else
-            sr_adjoint_mrhs<VT, L>(r0, r1, row_ptr, cols, vals, x, g, gx, gv, nrhs, lane);
-    }
+    for (int32_t s = s0 + wave; s < s1; s += nw)
+        sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
+                               valsT, x, g, gx, gv, nnz, nrhs, sym != 0, lds, lane);
 }
 
 // ------------------------------------------------------------------ plain CSR baseline
@@ -358,10 +618,11 @@ __global__ void __launch_bounds__(256) k_spmv_plain(int32_t n, const int32_t *__
 
 // ------------------------------------------------------------------ utilities
 
+// out[p] = in[idx[p]] for p < count.
 template <typename T>
-__global__ void k_fill_zero(T *__restrict__ p, int64_t count) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += int64_t(gridDim.x) * blockDim.x)
-        p[i] = T(0);
+__global__ void k_gather(const int32_t *__restrict__ idx, const T *__restrict__ in, T *__restrict__ out, int64_t count) {
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += int64_t(gridDim.x) * blockDim.x)
+        out[p] = in[idx[p]];
 }
 
 template <typename T>
@@ -433,21 +694,23 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
         for (int32_t s = s0 + wave; s < s1; s += nw) {
             const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
             if (nrhs == 1)
-                sr_forward<VT, L>(r0, r1, d.row_ptr, d.col_idx, vals, x, y, d.nnz, buf, lane);
+                sr_forward<VT, L, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, buf, lane);
             else
-                sr_forward_mrhs<VT, R>(r0, r1, d.row_ptr, d.col_idx, vals, x, y, nrhs, lane);
+                sr_forward_mrhs<VT, R, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, nrhs, lane);
         }
     }
 }
 
-template <typename VT, int L, int R>
+template <typename VT, int L, bool IND>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    unsigned char *lds = smem + size_t(wave) * kAdjointLds;
     const int32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t per = (nitems + gridDim.x - 1) / gridDim.x;
     const int32_t i0 = b * per, i1 = min(nitems, i0 + per);
@@ -455,30 +718,12 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
         const int32_t s0 = d.ssr_ptr[item.y], s1 = d.ssr_ptr[item.y + 1];
-        const VT *vals = static_cast<const VT *>(d.vals);
-        const X *x = static_cast<const X *>(d.x);
-        const X *g = static_cast<const X *>(d.g);
-        X *gx = static_cast<X *>(d.gx);
-        A *gv = static_cast<A *>(d.gv);
-        for (int32_t s = s0 + wave; s < s1; s += nw) {
-            const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
-            if (nrhs == 1)
-                sr_adjoint<VT, L>(r0, r1, d.row_ptr, d.col_idx, vals, x, g, gx, gv, lane);
-            else
-                sr_adjoint_mrhs<VT, R>(r0, r1, d.row_ptr, d.col_idx, vals, x, g, gx, gv, nrhs, lane);
-        }
+        for (int32_t s = s0 + wave; s < s1; s += nw)
+            sr_adjoint<VT, L, IND>(uniform(d.sr_ptr[s]), uniform(d.sr_ptr[s + 1]), d.row_ptr, d.col_idx, d.t_row_ptr,
+                                   d.t_col, d.t_src, static_cast<const VT *>(d.vals), static_cast<const X *>(d.x),
+                                   static_cast<const X *>(d.g), static_cast<X *>(d.gx), static_cast<A *>(d.gv), d.nnz,
+                                   nrhs, d.sym != 0, lds, lane);
     }
-}
-
-// Zero every matrix's grad_x block (blockIdx.y = matrix).
-template <typename X>
-__global__ void k_batch_zero_gx(const MatDesc *__restrict__ descs, int nrhs) {
-    const MatDesc d = descs[blockIdx.y];
-    if (!d.gx) return;
-    X *gx = static_cast<X *>(d.gx);
-    const int64_t total = int64_t(d.n) * nrhs;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < total; i += int64_t(gridDim.x) * blockDim.x)
-        gx[i] = X(0);
 }
 
 // ------------------------------------------------------------------ dispatch helpers
@@ -529,15 +774,6 @@ int grid_for(int64_t work, int block) {
     if (g < 1) g = 1;
     if (g > 65536) g = 65536;
     return int(g);
-}
-
-// Lanes per row used by the adjoint (its loads go straight to memory, so
-// lanes stride along a row): the power of two covering the typical row.
-int adjoint_lanes(const Arrays &a) {
-    const double r = a.n ? double(a.nnz) / a.n : 1.0;
-    int L = 4;
-    while (L < 64 && L < r) L <<= 1;
-    return L;
 }
 
 }  // namespace
@@ -597,23 +833,51 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                    void *gv, int nrhs, Shape s, hipStream_t st) {
     if (a.nssr == 0) return hipSuccess;
     const int block = s.waves * kWave;
+    // Values passed by the caller are reached through the transposed map; the
+    // handle's own values use its stored transposed copy.
+    const bool ind = vals != nullptr;
     return by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
         using X = typename Store<VT>::X;
         using A = typename Store<VT>::A;
-        if (gx) {
-            const int64_t cnt = int64_t(a.n) * nrhs;
-            hipLaunchKernelGGL((k_fill_zero<X>), dim3(grid_for(cnt, 256)), dim3(256), 0, st, static_cast<X *>(gx), cnt);
-        }
-        const int L = nrhs == 1 ? adjoint_lanes(a) : pow2_at_least(nrhs);
+        const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
+        const int L = nrhs == 1 ? s.lanes_per_row : pow2_at_least(nrhs);
         return by_lanes(L, [&](auto lc) -> hipError_t {
             constexpr int LL = decltype(lc)::value;
-            hipLaunchKernelGGL((k_adjoint_csrk<VT, LL>), dim3(a.nssr), dim3(block), 0, st, a.ssr_ptr, a.sr_ptr,
-                               a.row_ptr, a.col_idx, static_cast<const VT *>(vals), static_cast<const X *>(x),
-                               static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), nrhs);
+            const size_t lds = size_t(s.waves) * kAdjointLds;
+            if (ind)
+                hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, true>), dim3(a.nssr), dim3(block), lds, st, a.ssr_ptr,
+                                   a.sr_ptr, a.row_ptr, a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
+                                   static_cast<const X *>(x), static_cast<const X *>(g), static_cast<X *>(gx),
+                                   static_cast<A *>(gv), a.nnz, nrhs, int(a.sym));
+            else
+                hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, false>), dim3(a.nssr), dim3(block), lds, st, a.ssr_ptr,
+                                   a.sr_ptr, a.row_ptr, a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
+                                   static_cast<const X *>(x), static_cast<const X *>(g), static_cast<X *>(gx),
+                                   static_cast<A *>(gv), a.nnz, nrhs, int(a.sym));
             return hipGetLastError();
         });
     });
+}
+
+hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals, void *vals_t, hipStream_t st) {
+    if (a.nnz == 0) return hipSuccess;
+    const int grid = grid_for(a.nnz, 256);
+    switch (store) {
+    case CSRK_F64:
+        hipLaunchKernelGGL((k_gather<double>), dim3(grid), dim3(256), 0, st, a.t_src, static_cast<const double *>(vals),
+                           static_cast<double *>(vals_t), a.nnz);
+        break;
+    case CSRK_F32:
+        hipLaunchKernelGGL((k_gather<float>), dim3(grid), dim3(256), 0, st, a.t_src, static_cast<const float *>(vals),
+                           static_cast<float *>(vals_t), a.nnz);
+        break;
+    case CSRK_BF16:
+        hipLaunchKernelGGL((k_gather<uint16_t>), dim3(grid), dim3(256), 0, st, a.t_src,
+                           static_cast<const uint16_t *>(vals), static_cast<uint16_t *>(vals_t), a.nnz);
+        break;
+    }
+    return hipGetLastError();
 }
 
 hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st) {
@@ -661,20 +925,22 @@ hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems
     });
 }
 
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, int32_t nmat, int32_t max_n,
-                         csrk_dtype store, int nrhs, Shape s, int grid, hipStream_t st) {
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
+                         Shape s, int grid, bool ind, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
     const int R = pow2_at_least(nrhs);
     return by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
-        using X = typename Store<VT>::X;
-        const int zgrid = grid_for(int64_t(max_n) * nrhs, 256);
-        hipLaunchKernelGGL((k_batch_zero_gx<X>), dim3(zgrid < 1024 ? zgrid : 1024, nmat), dim3(256), 0, st, descs, nrhs);
         return by_lanes(nrhs == 1 ? s.lanes_per_row : R, [&](auto lc) -> hipError_t {
             constexpr int LL = decltype(lc)::value;
-            hipLaunchKernelGGL((k_batch_adjoint<VT, LL, LL>), dim3(grid), dim3(block), 0, st, descs, items, nitems,
-                               nrhs);
+            const size_t lds = size_t(s.waves) * kAdjointLds;
+            if (ind)
+                hipLaunchKernelGGL((k_batch_adjoint<VT, LL, true>), dim3(grid), dim3(block), lds, st, descs, items,
+                                   nitems, nrhs);
+            else
+                hipLaunchKernelGGL((k_batch_adjoint<VT, LL, false>), dim3(grid), dim3(block), lds, st, descs, items,
+                                   nitems, nrhs);
             return hipGetLastError();
         });
     });
@@ -689,7 +955,8 @@ int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj) {
         return by_lanes(nrhs == 1 ? s.lanes_per_row : R, [&](auto lc) -> hipError_t {
             constexpr int LL = decltype(lc)::value;
             if (adj)
-                return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, LL>, block, 0);
+                return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, false>, block,
+                                                                    size_t(s.waves) * kAdjointLds);
             return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, LL>, block,
                                                                 nrhs == 1 ? size_t(s.waves) * kStageBytes : 0);
         });

@@ -22,6 +22,14 @@ struct Arrays {
     const int32_t *sr_ptr = nullptr;
     const int32_t *ssr_ptr = nullptr;
     const int32_t *perm = nullptr;
+    // A'^T: row j lists column j of A' by increasing row (t_col) with each
+    // entry's position in A' (t_src).  For a symmetric pattern t_row_ptr and
+    // t_col are row_ptr and col_idx.
+    const int32_t *t_row_ptr = nullptr;
+    const int32_t *t_col = nullptr;
+    const int32_t *t_src = nullptr;
+    const void *vals_t = nullptr;  // the handle's values in A'^T order (aligned with t_col)
+    bool sym = false;              // pattern of A' is symmetric: A'^T has the pattern of A'
 };
 
 // Per-matrix record of a batched launch (device-resident table).
@@ -30,6 +38,9 @@ struct MatDesc {
     const int32_t *sr_ptr;
     const int32_t *row_ptr;
     const int32_t *col_idx;
+    const int32_t *t_row_ptr;
+    const int32_t *t_col;
+    const int32_t *t_src;
     const void *vals;
     const void *x;
     void *y;
@@ -39,6 +50,7 @@ struct MatDesc {
     int64_t nnz;
     int32_t n;
     int32_t nssr;
+    int32_t sym;
 };
 
 // Kernel-shape knobs: lanes per row in the reduction, wavefronts per workgroup.
@@ -53,14 +65,18 @@ hipError_t spmv_plain(const Arrays &a, csrk_dtype store, const void *vals, const
                       Shape s, hipStream_t st);
 hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const void *x, const void *g, void *gx,
                    void *gv, int nrhs, Shape s, hipStream_t st);
+// vals_t[p] = vals[t_src[p]]: the values in A'^T order.
+hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals, void *vals_t, hipStream_t st);
 hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st);
 hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtype store, hipStream_t st);
 
 // Batched persistent launches over `nitems` (matrix, super-super-row) items.
 hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
                          Shape s, int grid, hipStream_t st);
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, int32_t nmat, int32_t max_n,
-                         csrk_dtype store, int nrhs, Shape s, int grid, hipStream_t st);
+// `ind`: the descriptors' vals are caller values in CSR-k order (reached
+// through t_src); otherwise they are the handles' transposed copies.
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
+                         Shape s, int grid, bool ind, hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint);

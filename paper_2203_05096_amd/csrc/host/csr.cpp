@@ -57,6 +57,31 @@ Permuted permute(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, cons
     return p;
 }
 
+Transposed transpose_index(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx) {
+    Transposed t;
+    const int64_t nnz = row_ptr[n];
+    t.t_row_ptr.assign(static_cast<size_t>(n) + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k) ++t.t_row_ptr[col_idx[k] + 1];
+    for (int32_t j = 0; j < n; ++j) t.t_row_ptr[j + 1] += t.t_row_ptr[j];
+    t.t_col.resize(nnz);
+    t.t_src.resize(nnz);
+    std::vector<int32_t> fill(t.t_row_ptr.begin(), t.t_row_ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            const int32_t p = fill[col_idx[k]]++;
+            t.t_col[p] = i;
+            t.t_src[p] = k;
+        }
+    t.symmetric = (t.t_row_ptr == row_ptr) && (t.t_col == col_idx);
+    if (t.symmetric) {
+        t.t_row_ptr.clear();
+        t.t_row_ptr.shrink_to_fit();
+        t.t_col.clear();
+        t.t_col.shrink_to_fit();
+    }
+    return t;
+}
+
 int32_t bandwidth(int32_t n, const int32_t *row_ptr, const int32_t *col_idx) {
     int64_t bw = 0;
     for (int32_t i = 0; i < n; ++i)

@@ -101,6 +101,18 @@ struct Permuted {
 Permuted permute(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
                  const std::vector<int32_t> &perm);
 
+// Transposed index structure of A' used by the adjoint: row j of A'^T lists
+// the entries of column j of A' by increasing row, as (row, position in A').
+// When the pattern is symmetric, t_row_ptr / t_col equal row_ptr / col_idx
+// and only t_src (the position of each entry's mirror) is needed.
+struct Transposed {
+    bool symmetric = true;
+    std::vector<int32_t> t_row_ptr;
+    std::vector<int32_t> t_col;
+    std::vector<int32_t> t_src;
+};
+Transposed transpose_index(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx);
+
 // Row statistics (Section 5.3 / Table 1).
 struct Stats {
     double rdensity = 0, row_variance = 0, symmetry = 1;
