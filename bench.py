@@ -43,6 +43,26 @@ def adj_bytes(n, nnz, nsr, nssr, val_bytes=8, vec_bytes=8, gv_bytes=8, nrhs=1):
     return nnz * (4 + val_bytes + gv_bytes) + n * (4 + 3 * vec_bytes * nrhs) + 4 * (nsr + nssr)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_csrk_3d7pt128_f64.txt")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2203_05096_amd", "csrc", "device", "kernels.hip")
+
+
+def profiled_traffic(kernel_prefix):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated) recorded for this kernel source, else None."""
+    import hashlib
+    try:
+        text = "".join(l for l in open(TRAFFIC_FILE) if not l.startswith("#"))
+        rec = json.loads(text)
+        if rec["kernel_source_sha256"] != hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest():
+            return None
+        for name, k in rec["kernels"].items():
+            if name.startswith(kernel_prefix):
+                return int(k["fetch_bytes"] + k["write_bytes"])
+    except (OSError, ValueError, KeyError):
+        return None
+    return None
+
+
 def cpu_model():
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
@@ -172,7 +192,8 @@ def main():
     value = flops_step / (wall_ms * 1e-3) / 1e9
     fwd_gbs = fb / (fwd_ms * 1e-3) / 1e9
     adj_gbs = ab / (adj_ms * 1e-3) / 1e9
-    dom = ("forward", fwd_ms, fb, fwd_gbs) if fwd_ms >= adj_ms else ("adjoint", adj_ms, ab, adj_gbs)
+    dom = ("forward", fwd_ms, fb, fwd_gbs, "k_spmv_csrk") if fwd_ms >= adj_ms else \
+        ("adjoint", adj_ms, ab, adj_gbs, "k_adjoint_csrk")
     log(f"step {wall_ms:.4f} ms; forward {fwd_ms * 1e3:.1f} us {fwd_gbs:.0f} GB/s; "
         f"adjoint {adj_ms * 1e3:.1f} us {adj_gbs:.0f} GB/s")
 
@@ -264,7 +285,8 @@ def main():
         "adjoint": {"us": round(adj_ms * 1e3, 2), "GFLOPs": round(3 * A.nnz / adj_ms / 1e6, 1),
                     "GBs": round(adj_gbs, 1), "bytes": ab},
         "roofline": {"bound": "hbm", "kernel": dom[0], "achieved": round(dom[3], 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(dom[3] / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(dom[3] / HBM_PEAK_GBS, 4), "traffic": profiled_traffic(dom[4]),
+                     "algorithmic_bytes": dom[2]},
         "cpu_baseline": cpu,
         "extras": extras,
     }

@@ -29,7 +29,8 @@ namespace dev {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kStageBytes = 4096;  // LDS staging window per wavefront
+constexpr int kStageEntries = 512;                 // nonzeros staged per window and wavefront
+constexpr int kStageBytes = kStageEntries * 8;     // LDS for one window of products (FP64 worst case)
 constexpr int kXcds = 8;
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
@@ -137,7 +138,7 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
-    constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int CAP = kStageEntries;
     constexpr int U = CAP / (kWave * V);  // unrolled stream steps covering CAP entries
     constexpr int WIN = CAP - V;          // window limit: an unaligned window still fits U steps
     static_assert(U >= 1 && U * kWave * V == CAP, "staging area must be a whole number of steps");
@@ -223,7 +224,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                                     typename Store<VT>::X *__restrict__ y, int64_t nnz) {
     using A = typename Store<VT>::A;
-    constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int CAP = kStageEntries;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
@@ -419,7 +420,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
-    constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int CAP = kStageEntries;
     constexpr int U = CAP / (kWave * V);
     constexpr int WIN = CAP - V;
     typedef A AV __attribute__((ext_vector_type(V)));
@@ -475,6 +476,24 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
             gwin[lane] = A(g[ra + lane]);
             for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
         }
+        // All x gathers, then all g gathers, before any LDS or store work: the
+        // compiler does not move them past those on its own, and issuing them
+        // together keeps far more requests in flight.
+        A xs[U][V], gs[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                xs[u][e] = (k >= cs && k < ce) ? A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                gs[u][e] = (k >= cs && k < ce) ? A(g[c[u][e]]) : A(0);
+            }
         wave_lds_sync();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -484,8 +503,8 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
             for (int e = 0; e < V; ++e) {
                 const int64_t k = pos + e;
                 const bool ok = k >= cs && k < ce;
-                const A xj = ok ? A(x[c[u][e]]) : A(0);
-                const A gj = ok ? A(g[c[u][e]]) : A(0);
+                const A xj = xs[u][e];
+                const A gj = gs[u][e];
                 gvv[e] = ok ? gwin[rowid[k - cs]] * xj : A(0);
                 if (ok) buf[k - cs] = v[u][e] * gj;
             }
@@ -551,8 +570,9 @@ __device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t
     }
 }
 
-// LDS bytes per wavefront of the adjoint kernels.
-constexpr int kAdjointLds = kStageBytes + 1024 + 64 * 8;
+// LDS bytes per wavefront of the adjoint kernels: products, a one-byte row map
+// per staged entry, g of 64 rows.
+constexpr int kAdjointLds = kStageBytes + kStageEntries + 64 * 8;
 
 template <typename VT, int L, bool IND>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
@@ -675,7 +695,7 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    constexpr int CAP = kStageBytes / int(sizeof(A));
+    constexpr int CAP = kStageEntries;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);

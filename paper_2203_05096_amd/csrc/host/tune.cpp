@@ -28,7 +28,7 @@ int case_of(double r) {
 // MI355X fit of the same logarithmic form.  SRS (rows per super-row) is sized
 // so one super-row's nonzeros fill a wavefront's LDS staging window; SSRS
 // (super-rows per workgroup) keeps every wavefront of the workgroup busy.
-constexpr double kMiSsrsA = 8.0, kMiSsrsB = 0.0;
+constexpr double kMiSsrsA = 4.0, kMiSsrsB = 0.0;
 constexpr double kMiSrsA = 133.0, kMiSrsB = 35.5;
 
 int32_t clamp_size(int64_t v, int64_t hi) { return static_cast<int32_t>(std::max<int64_t>(1, std::min(v, hi))); }
