@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <initializer_list>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -590,6 +591,16 @@ csrk::dev::MatDesc *upload_descs(csrk_batch b, int which, const void *const *val
     return b->d_descs[which];
 }
 
+// True when every non-null pointer of every array is 16-byte aligned.
+bool all_aligned16(std::initializer_list<const void *const *> arrays, size_t count) {
+    for (const void *const *a : arrays) {
+        if (!a) continue;
+        for (size_t i = 0; i < count; ++i)
+            if (a[i] && reinterpret_cast<uintptr_t>(a[i]) % 16) return false;
+    }
+    return true;
+}
+
 int batch_grid(csrk_batch b, int nrhs, bool adj) {
     const int per_cu = csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj);
     const int64_t g = int64_t(b->cus) * per_cu;
@@ -610,8 +621,9 @@ csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *c
         DeviceScope ds(b->device);
         hipStream_t st = static_cast<hipStream_t>(stream);
         csrk::dev::MatDesc *descs = upload_descs(b, 0, vals, x, y, nullptr, nullptr, nullptr, st);
+        const bool vec = all_aligned16({x, reinterpret_cast<const void *const *>(y)}, b->handles.size());
         hip_check(csrk::dev::batch_forward(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
-                                           batch_grid(b, nrhs, false), st),
+                                           batch_grid(b, nrhs, false), vec, st),
                   "csrk_batch_spmv launch");
         return CSRK_OK;
     });
@@ -632,8 +644,9 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         hipStream_t st = static_cast<hipStream_t>(stream);
         csrk::dev::MatDesc *descs = upload_descs(b, 1, vals, x, nullptr, g, grad_x, grad_vals, st);
         const bool ind = vals && std::any_of(vals, vals + b->handles.size(), [](const void *p) { return p != nullptr; });
+        const bool vec = all_aligned16({x, g, reinterpret_cast<const void *const *>(grad_x)}, b->handles.size());
         hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
-                                           batch_grid(b, nrhs, true), ind, st),
+                                           batch_grid(b, nrhs, true), ind, vec, st),
                   "csrk_batch_spmv_adjoint launch");
         return CSRK_OK;
     });

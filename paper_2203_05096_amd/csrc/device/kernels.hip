@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
+#include <type_traits>
 
 #include "launch.hpp"
 
@@ -237,51 +239,198 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
                                  buf, lane);
 }
 
-// y for one super-row, nrhs right-hand sides (row-major): R lanes per row cover
-// R consecutive columns of the block; 64/R rows per pass.  Values are vals[k]
-// or vals[src[k]] (IND).
-template <typename VT, int R, bool IND>
+// LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
+// (value, column) pairs.
+constexpr int kMrhsLds = kStageEntries * (8 + 4);
+
+// VX consecutive right-hand-side columns starting at p (16-byte aligned when VX > 1).
+template <typename X, int VX>
+__device__ __forceinline__ void load_cols(const X *__restrict__ p, X (&out)[VX]) {
+    if constexpr (VX == 1) {
+        out[0] = p[0];
+    } else {
+        typedef X XV __attribute__((ext_vector_type(VX)));
+        const XV t = *reinterpret_cast<const XV *>(p);
+#pragma unroll
+        for (int e = 0; e < VX; ++e) out[e] = t[e];
+    }
+}
+
+template <typename X, int VX>
+__device__ __forceinline__ void store_cols(X *__restrict__ p, const X (&in)[VX]) {
+    if constexpr (VX == 1) {
+        p[0] = in[0];
+    } else {
+        typedef X XV __attribute__((ext_vector_type(VX)));
+        XV t;
+#pragma unroll
+        for (int e = 0; e < VX; ++e) t[e] = in[e];
+        *reinterpret_cast<XV *>(p) = t;
+    }
+}
+
+// Sum over the lanes that share lane % RL (the entry slices of a long row).
+template <int RL, typename T>
+__device__ __forceinline__ T slice_sum(T v) {
+#pragma unroll
+    for (int off = kWave / 2; off >= RL; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// y for rows r0..r1-1 with nrhs right-hand sides (row-major n x nrhs).  Per
+// window of whole rows, the (value, column) pairs are streamed into LDS with
+// 16-byte loads; then RL lanes per row each accumulate VX consecutive columns,
+// gathering VX-wide slices of the x rows (64/RL rows per pass).  Values are
+// vals[k] or vals[src[k]] (IND).  VX > 1 requires nrhs % VX == 0 and 16-byte
+// aligned x / y.
+template <typename VT, int RL, int VX, bool IND>
 __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
                                                 const VT *__restrict__ vals,
                                                 const typename Store<VT>::X *__restrict__ x,
-                                                typename Store<VT>::X *__restrict__ y, int nrhs, int lane) {
+                                                typename Store<VT>::X *__restrict__ y, int64_t nnz, int nrhs,
+                                                unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    const int c = lane % R;
-    const int rr = lane / R;
-    for (int cb = 0; cb < nrhs; cb += R) {
-        const int col = cb + c;
-        const bool cok = col < nrhs;
-        for (int32_t rb = r0; rb < r1; rb += kWave / R) {
-            const int32_t row = rb + rr;
-            if (row < r1 && cok) {
-                A acc = 0;
-                const int32_t kb = row_ptr[row], ke = row_ptr[row + 1];
-#pragma unroll 4
-                for (int32_t k = kb; k < ke; ++k)
-                    acc += Store<VT>::widen(vals[IND ? src[k] : k]) * A(x[int64_t(cols[k]) * nrhs + col]);
-                y[int64_t(row) * nrhs + col] = X(acc);
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * V);
+    constexpr int WIN = CAP - V;
+    constexpr int RPP = kWave / RL;  // rows per pass
+    constexpr int CPP = RL * VX;     // columns per pass
+    A *sval = reinterpret_cast<A *>(lds);
+    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
+    const int q = lane % RL;
+    const int rsub = lane / RL;
+    int32_t ra = r0;
+    int32_t cs = uniform(row_ptr[r0]);
+    int32_t my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+    while (ra < r1) {
+        const bool fits = (ra + lane < r1) && (my_end - cs <= WIN);
+        const uint64_t mask = __ballot(fits);
+        const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
+        if (nrows == 0) {
+            // Row ra alone exceeds the window: entry slices of RPP lanes, RL lanes over columns.
+            const int32_t re = uniform(__shfl(my_end, 0));
+            for (int cb = 0; cb < nrhs; cb += CPP) {
+                const int col0 = cb + q * VX;
+                const bool cok = col0 < nrhs;
+                A acc[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) acc[e] = A(0);
+                for (int64_t k = int64_t(cs) + rsub; k < re; k += RPP) {
+                    if (!cok) continue;
+                    const A a = Store<VT>::widen(vals[IND ? src[k] : k]);
+                    X xv[VX];
+                    load_cols<X, VX>(x + int64_t(cols[k]) * nrhs + col0, xv);
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) acc[e] += a * A(xv[e]);
+                }
+                X out[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) out[e] = X(slice_sum<RL>(acc[e]));
+                if (rsub == 0 && cok) store_cols<X, VX>(y + int64_t(ra) * nrhs + col0, out);
+            }
+            cs = re;
+            ++ra;
+            my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+            continue;
+        }
+        const int32_t ce = uniform(__shfl(my_end, nrows - 1));
+        const int32_t nra = ra + nrows;
+        const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
+        const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+        A v[U][V];
+        int32_t c[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < ce) {
+                load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                if (k >= cs && k < ce) {
+                    sval[k - cs] = v[u][e];
+                    scol[k - cs] = c[u][e];
+                }
+            }
+        wave_lds_sync();
+#pragma unroll 1
+        for (int b = 0; b < nrows; b += RPP) {
+            const int rr = b + rsub;
+            const bool act = rr < nrows;
+            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+            const int32_t rbeg = rr == 0 ? 0 : prev;
+            if (!act) continue;
+            for (int cb = 0; cb < nrhs; cb += CPP) {
+                const int col0 = cb + q * VX;
+                if (col0 >= nrhs) continue;
+                A acc[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) acc[e] = A(0);
+                // four entries at a time: their x slices are all requested before any is used
+                for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
+                    X xv[4][VX];
+                    A a[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const bool ok = k0 + t < rend;
+                        a[t] = ok ? sval[k0 + t] : A(0);
+                        if (ok) {
+                            load_cols<X, VX>(x + int64_t(scol[k0 + t]) * nrhs + col0, xv[t]);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) xv[t][e] = X(0);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) acc[e] += a[t] * A(xv[t][e]);
+                }
+                X out[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) out[e] = X(acc[e]);
+                store_cols<X, VX>(y + int64_t(ra + rr) * nrhs + col0, out);
+            }
+        }
+        wave_lds_sync();
+        cs = ce;
+        ra = nra;
+        my_end = next_end;
     }
 }
 
-template <typename VT, int R>
+template <typename VT, int RL, int VX>
 __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restrict__ ssr_ptr,
                                                          const int32_t *__restrict__ sr_ptr,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ cols, const VT *__restrict__ vals,
                                                          const typename Store<VT>::X *__restrict__ x,
-                                                         typename Store<VT>::X *__restrict__ y, int nrhs) {
+                                                         typename Store<VT>::X *__restrict__ y, int64_t nnz,
+                                                         int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    unsigned char *lds = smem + size_t(wave) * kMrhsLds;
     const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward_mrhs<VT, R, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y,
-                                      nrhs, lane);
+        sr_forward_mrhs<VT, RL, VX, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals,
+                                           x, y, nnz, nrhs, lds, lane);
 }
 
 // ------------------------------------------------------------------ adjoint
@@ -295,9 +444,11 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
 // Both use the rows of the same super-row, so the SSR -> workgroup and
 // SR -> wavefront mapping carries over unchanged.
 
-// grad_vals for rows r0..r1-1, single right-hand side.  Each window's rows
-// write their local index over their entries in an LDS byte map, so the stream
-// can find g_i for any entry.
+// grad_vals for rows r0..r1-1, single right-hand side, in windows of whole
+// rows like the forward.  Each window's rows write their local index over
+// their entries in an LDS byte map, so the stream can find g_i for any entry.
+// All column loads of a window are issued first, then all x gathers, then the
+// 16-byte stores.
 template <typename VT>
 __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                              const int32_t *__restrict__ cols,
@@ -307,17 +458,19 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
                                              unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
     constexpr int VA = 16 / int(sizeof(A));  // grad_vals entries per 16-byte store
-    constexpr int MAPB = kStageBytes - kWave * int(sizeof(A));
-    constexpr int WIN = MAPB - VA;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * VA);
+    constexpr int WIN = CAP - VA;
+    static_assert(U >= 1 && U * kWave * VA == CAP, "window must be a whole number of steps");
     typedef A AV __attribute__((ext_vector_type(VA)));
     typedef int32_t CV __attribute__((ext_vector_type(VA)));
     unsigned char *rowid = lds;
-    A *gwin = reinterpret_cast<A *>(lds + MAPB);
+    A *gwin = reinterpret_cast<A *>(lds + CAP);
     int32_t ra = r0;
     int32_t cs = uniform(row_ptr[r0]);
+    int32_t my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
     while (ra < r1) {
         const bool in = ra + lane < r1;
-        const int32_t my_end = in ? row_ptr[ra + lane + 1] : 0;
         const bool fits = in && (my_end - cs <= WIN);
         const uint64_t mask = __ballot(fits);
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
@@ -327,30 +480,48 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
             for (int64_t k = int64_t(cs) + lane; k < re; k += kWave) gv[k] = gi * A(x[cols[k]]);
             cs = re;
             ++ra;
+            my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
             continue;
         }
         const int32_t ce = uniform(__shfl(my_end, nrows - 1));
+        const int32_t nra = ra + nrows;
+        const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
         const int32_t prev_end = __shfl(my_end, lane > 0 ? lane - 1 : 0);
+        const int64_t base = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA;
+        int32_t c[U][VA];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * VA;
+            if (pos < ce && pos + VA <= nnz) {
+                const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[u][e] = cv[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[u][e] = (pos < ce && pos + e < nnz) ? cols[pos + e] : 0;
+            }
+        }
         if (lane < nrows) {
             gwin[lane] = A(g[ra + lane]);
             for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
         }
-        wave_lds_sync();
-        for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ce; pos += int64_t(kWave) * VA) {
-            int32_t c[VA];
-            if (pos + VA <= nnz) {
-                const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+        A xs[U][VA];
 #pragma unroll
-                for (int e = 0; e < VA; ++e) c[e] = cv[e];
-            } else {
+        for (int u = 0; u < U; ++u)
 #pragma unroll
-                for (int e = 0; e < VA; ++e) c[e] = pos + e < nnz ? cols[pos + e] : 0;
+            for (int e = 0; e < VA; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * VA + e;
+                xs[u][e] = (k >= cs && k < ce) ? A(x[c[u][e]]) : A(0);
             }
+        wave_lds_sync();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * VA;
             A out[VA];
 #pragma unroll
             for (int e = 0; e < VA; ++e) {
                 const int64_t k = pos + e;
-                out[e] = (k >= cs && k < ce) ? gwin[rowid[k - cs]] * A(x[c[e]]) : A(0);
+                out[e] = (k >= cs && k < ce) ? gwin[rowid[k - cs]] * xs[u][e] : A(0);
             }
             if (pos >= cs && pos + VA <= ce) {
                 AV ov;
@@ -367,37 +538,153 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
         }
         wave_lds_sync();
         cs = ce;
-        ra += nrows;
+        ra = nra;
+        my_end = next_end;
     }
 }
 
-// grad_vals for several right-hand sides: R lanes per row cover R columns of
-// the block and reduce sum_c g[i,c] x[j,c] per entry with wavefront shuffles.
-template <typename VT, int R>
+// grad_vals for several right-hand sides: grad_vals[k] = sum_c g[i,c] x[j,c].
+// Per window, the column indices are streamed into LDS; RL lanes per row each
+// take VX columns of g_i and of the gathered x_j rows, the partial dot
+// products are summed across the RL lanes with shuffles into LDS, and the
+// window's results are written out with 16-byte stores.
+template <typename VT, int RL, int VX>
 __device__ __forceinline__ void sr_grad_vals_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ cols,
                                                   const typename Store<VT>::X *__restrict__ x,
                                                   const typename Store<VT>::X *__restrict__ g,
-                                                  typename Store<VT>::A *__restrict__ gv, int nrhs, int lane) {
+                                                  typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
+                                                  unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
-    const int c = lane % R;
-    const int rr = lane / R;
-    for (int cb = 0; cb < nrhs; cb += R) {
-        const int col = cb + c;
-        const bool cok = col < nrhs;
-        for (int32_t rb = r0; rb < r1; rb += kWave / R) {
-            const int32_t row = rb + rr;
-            if (row < r1) {
-                const A gi = cok ? A(g[int64_t(row) * nrhs + col]) : A(0);
-                const int32_t ke = row_ptr[row + 1];
-                for (int32_t k = row_ptr[row]; k < ke; ++k) {
-                    const int64_t j = cols[k];
-                    A p = cok ? gi * A(x[j * nrhs + col]) : A(0);
-                    p = group_sum<R>(p);
-                    if (c == 0) gv[k] = cb == 0 ? p : gv[k] + p;
+    using X = typename Store<VT>::X;
+    constexpr int VC = 4;  // column indices per 16-byte load
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * VC);
+    constexpr int WIN = CAP - VC;
+    constexpr int RPP = kWave / RL;
+    constexpr int CPP = RL * VX;
+    constexpr int VA = 16 / int(sizeof(A));  // grad_vals entries per 16-byte store
+    typedef int32_t CV __attribute__((ext_vector_type(VC)));
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    int32_t *scol = reinterpret_cast<int32_t *>(lds);
+    A *sgv = reinterpret_cast<A *>(lds + CAP * sizeof(int32_t));
+    const int q = lane % RL;
+    const int rsub = lane / RL;
+    int32_t ra = r0;
+    int32_t cs = uniform(row_ptr[r0]);
+    int32_t my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+    while (ra < r1) {
+        const bool fits = (ra + lane < r1) && (my_end - cs <= WIN);
+        const uint64_t mask = __ballot(fits);
+        const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
+        if (nrows == 0) {
+            const int32_t re = uniform(__shfl(my_end, 0));
+            // entry slices of RPP lanes; each slice's RL lanes reduce one entry
+            for (int64_t kb = int64_t(cs); kb < re; kb += RPP) {
+                const int64_t k = kb + rsub;
+                const bool kok = k < re;
+                const int64_t j = kok ? cols[k] : 0;
+                A p = 0;
+                for (int cb = 0; cb < nrhs; cb += CPP) {
+                    const int col0 = cb + q * VX;
+                    if (!kok || col0 >= nrhs) continue;
+                    X gi[VX], xv[VX];
+                    load_cols<X, VX>(g + int64_t(ra) * nrhs + col0, gi);
+                    load_cols<X, VX>(x + j * nrhs + col0, xv);
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) p += A(gi[e]) * A(xv[e]);
+                }
+                p = group_sum<RL>(p);
+                if (kok && q == 0) gv[k] = p;
+            }
+            cs = re;
+            ++ra;
+            my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
+            continue;
+        }
+        const int32_t ce = uniform(__shfl(my_end, nrows - 1));
+        const int32_t nra = ra + nrows;
+        const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
+        const int64_t base = int64_t(cs & ~(VC - 1)) + int64_t(lane) * VC;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * VC;
+            int32_t c[VC];
+            if (pos < ce && pos + VC <= nnz) {
+                const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+#pragma unroll
+                for (int e = 0; e < VC; ++e) c[e] = cv[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VC; ++e) c[e] = (pos < ce && pos + e < nnz) ? cols[pos + e] : 0;
+            }
+#pragma unroll
+            for (int e = 0; e < VC; ++e) {
+                const int64_t k = pos + e;
+                if (k >= cs && k < ce) scol[k - cs] = c[e];
+            }
+        }
+        wave_lds_sync();
+#pragma unroll 1
+        for (int b = 0; b < nrows; b += RPP) {
+            const int rr = b + rsub;
+            const bool act = rr < nrows;
+            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+            const int32_t rbeg = rr == 0 ? 0 : prev;
+            if (!act) continue;  // a row's RL lanes are active or idle together
+            for (int cb = 0; cb < nrhs; cb += CPP) {
+                const int col0 = cb + q * VX;
+                const bool cok = col0 < nrhs;
+                X gi[VX];
+                if (cok) {
+                    load_cols<X, VX>(g + int64_t(ra + rr) * nrhs + col0, gi);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) gi[e] = X(0);
+                }
+                for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
+                    X xv[4][VX];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        if (cok && k0 + t < rend) {
+                            load_cols<X, VX>(x + int64_t(scol[k0 + t]) * nrhs + col0, xv[t]);
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < VX; ++e) xv[t][e] = X(0);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        A p = 0;
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) p += A(gi[e]) * A(xv[t][e]);
+                        p = group_sum<RL>(p);
+                        if (q == 0 && k0 + t < rend) sgv[k0 + t] = cb == 0 ? p : sgv[k0 + t] + p;
+                    }
                 }
             }
         }
+        wave_lds_sync();
+        // the window's grad_vals leave LDS as 16-byte stores
+        for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ce; pos += int64_t(kWave) * VA) {
+            if (pos >= cs && pos + VA <= ce) {
+                AV ov;
+#pragma unroll
+                for (int e = 0; e < VA; ++e) ov[e] = sgv[pos + e - cs];
+                *reinterpret_cast<AV *>(gv + pos) = ov;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) {
+                    const int64_t k = pos + e;
+                    if (k >= cs && k < ce) gv[k] = sgv[k - cs];
+                }
+            }
+        }
+        wave_lds_sync();
+        cs = ce;
+        ra = nra;
+        my_end = next_end;
     }
 }
 
@@ -542,9 +829,9 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
     }
 }
 
-// Both gradients of one super-row.  `valsT` holds the transposed values
-// (aligned with t_col) unless IND, in which case it holds the caller's values
-// in CSR-k order and each transposed value is vals[t_src[p]].
+// Both gradients of one super-row, single right-hand side.  `valsT` holds the
+// transposed values (aligned with t_col) unless IND, in which case it holds the
+// caller's values in CSR-k order and each transposed value is vals[t_src[p]].
 template <typename VT, int L, bool IND>
 __device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                            const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr,
@@ -552,27 +839,38 @@ __device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t
                                            const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
                                            const typename Store<VT>::X *__restrict__ g,
                                            typename Store<VT>::X *__restrict__ gx,
-                                           typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, bool sym,
+                                           typename Store<VT>::A *__restrict__ gv, int64_t nnz, bool sym,
                                            unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
-    if (nrhs == 1) {
-        if (sym && gx && gv) {
-            sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane);
-            return;
-        }
-        if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane);
-        if (gx)
-            sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, reinterpret_cast<A *>(lds),
-                                   lane);
-    } else {
-        if (gv) sr_grad_vals_mrhs<VT, L>(r0, r1, row_ptr, cols, x, g, gv, nrhs, lane);
-        if (gx) sr_forward_mrhs<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nrhs, lane);
+    if (sym && gx && gv) {
+        sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane);
+        return;
     }
+    if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane);
+    if (gx)
+        sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, reinterpret_cast<A *>(lds), lane);
+}
+
+// Both gradients of one super-row, several right-hand sides (RL lanes x VX columns per row).
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void sr_adjoint_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
+                                                const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr,
+                                                const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src,
+                                                const VT *__restrict__ valsT,
+                                                const typename Store<VT>::X *__restrict__ x,
+                                                const typename Store<VT>::X *__restrict__ g,
+                                                typename Store<VT>::X *__restrict__ gx,
+                                                typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
+                                                unsigned char *__restrict__ lds, int lane) {
+    if (gv) sr_grad_vals_mrhs<VT, RL, VX>(r0, r1, row_ptr, cols, x, g, gv, nnz, nrhs, lds, lane);
+    if (gx) sr_forward_mrhs<VT, RL, VX, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, nrhs, lds, lane);
 }
 
 // LDS bytes per wavefront of the adjoint kernels: products, a one-byte row map
 // per staged entry, g of 64 rows.
 constexpr int kAdjointLds = kStageBytes + kStageEntries + 64 * 8;
+// LDS bytes per wavefront of the batched kernels (any direction, any nrhs).
+constexpr int kBatchLds = kMrhsLds > kAdjointLds ? kMrhsLds : kAdjointLds;
 
 template <typename VT, int L, bool IND>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
@@ -584,8 +882,7 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
                                                        const typename Store<VT>::X *__restrict__ x,
                                                        const typename Store<VT>::X *__restrict__ g,
                                                        typename Store<VT>::X *__restrict__ gx,
-                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
-                                                       int sym) {
+                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
@@ -595,7 +892,26 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
-                               valsT, x, g, gx, gv, nnz, nrhs, sym != 0, lds, lane);
+                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane);
+}
+
+template <typename VT, int RL, int VX, bool IND>
+__global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
+    const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr, const int32_t *__restrict__ t_col,
+    const int32_t *__restrict__ t_src, const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
+    const typename Store<VT>::X *__restrict__ g, typename Store<VT>::X *__restrict__ gx,
+    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
+    unsigned char *lds = smem + size_t(wave) * kMrhsLds;
+    const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
+    for (int32_t s = s0 + wave; s < s1; s += nw)
+        sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
+                                         t_src, valsT, x, g, gx, gv, nnz, nrhs, lds, lane);
 }
 
 // ------------------------------------------------------------------ plain CSR baseline
@@ -689,18 +1005,18 @@ __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ 
 
 // Persistent batched forward: logical block b takes the contiguous item range
 // [b*per, (b+1)*per) of the (matrix, SSR) work list; logical indices are laid
-// out so each XCD owns a contiguous part of the list.
-template <typename VT, int L, int R>
+// out so each XCD owns a contiguous part of the list.  L is the lanes per row
+// (single right-hand side) or per row group (several: L lanes x VX columns).
+template <typename VT, int L, int VX>
 __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    constexpr int CAP = kStageEntries;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    A *buf = reinterpret_cast<A *>(smem) + wave * CAP;
+    unsigned char *lds = smem + size_t(wave) * kBatchLds;
     const int32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t per = (nitems + gridDim.x - 1) / gridDim.x;
     const int32_t i0 = b * per, i1 = min(nitems, i0 + per);
@@ -714,14 +1030,16 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
         for (int32_t s = s0 + wave; s < s1; s += nw) {
             const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
             if (nrhs == 1)
-                sr_forward<VT, L, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, buf, lane);
+                sr_forward<VT, L, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz,
+                                         reinterpret_cast<A *>(lds), lane);
             else
-                sr_forward_mrhs<VT, R, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, nrhs, lane);
+                sr_forward_mrhs<VT, L, VX, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
+                                                  lane);
         }
     }
 }
 
-template <typename VT, int L, bool IND>
+template <typename VT, int L, int VX, bool IND>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
@@ -730,7 +1048,7 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    unsigned char *lds = smem + size_t(wave) * kAdjointLds;
+    unsigned char *lds = smem + size_t(wave) * kBatchLds;
     const int32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t per = (nitems + gridDim.x - 1) / gridDim.x;
     const int32_t i0 = b * per, i1 = min(nitems, i0 + per);
@@ -738,11 +1056,20 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
         const int32_t s0 = d.ssr_ptr[item.y], s1 = d.ssr_ptr[item.y + 1];
-        for (int32_t s = s0 + wave; s < s1; s += nw)
-            sr_adjoint<VT, L, IND>(uniform(d.sr_ptr[s]), uniform(d.sr_ptr[s + 1]), d.row_ptr, d.col_idx, d.t_row_ptr,
-                                   d.t_col, d.t_src, static_cast<const VT *>(d.vals), static_cast<const X *>(d.x),
-                                   static_cast<const X *>(d.g), static_cast<X *>(d.gx), static_cast<A *>(d.gv), d.nnz,
-                                   nrhs, d.sym != 0, lds, lane);
+        const VT *vals = static_cast<const VT *>(d.vals);
+        const X *x = static_cast<const X *>(d.x);
+        const X *g = static_cast<const X *>(d.g);
+        X *gx = static_cast<X *>(d.gx);
+        A *gv = static_cast<A *>(d.gv);
+        for (int32_t s = s0 + wave; s < s1; s += nw) {
+            const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
+            if (nrhs == 1)
+                sr_adjoint<VT, L, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x, g, gx,
+                                       gv, d.nnz, d.sym != 0, lds, lane);
+            else
+                sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x,
+                                                g, gx, gv, d.nnz, nrhs, lds, lane);
+        }
     }
 }
 
@@ -789,6 +1116,27 @@ hipError_t by_lanes(int L, F &&f) {
     return hipErrorInvalidValue;
 }
 
+// Columns per lane for multi-right-hand-side kernels: 16 bytes of columns when
+// nrhs is a multiple of that width and every block pointer is 16-byte aligned.
+template <typename X>
+int vec_cols(int nrhs, std::initializer_list<const void *> ptrs) {
+    constexpr int VXM = 16 / int(sizeof(X));
+    if (nrhs % VXM) return 1;
+    for (const void *p : ptrs)
+        if (p && reinterpret_cast<uintptr_t>(p) % 16) return 1;
+    return VXM;
+}
+
+// Calls f with std::integral_constant<int, VX> for VX in {1, 16 / sizeof(X)}.
+template <typename X, typename F>
+hipError_t by_vx(int vx, F &&f) {
+    if (vx == 1) return f(std::integral_constant<int, 1>{});
+    return f(std::integral_constant<int, 16 / int(sizeof(X))>{});
+}
+
+// Lanes per row for a multi-right-hand-side kernel with VX columns per lane.
+int rhs_lanes(int nrhs, int vx) { return pow2_at_least((nrhs + vx - 1) / vx); }
+
 int grid_for(int64_t work, int block) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -814,12 +1162,17 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
                 return hipGetLastError();
             });
         }
-        return by_lanes(pow2_at_least(nrhs), [&](auto rc) -> hipError_t {
-            constexpr int R = decltype(rc)::value;
-            hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, R>), dim3(a.nssr), dim3(block), 0, st, a.ssr_ptr, a.sr_ptr,
-                               a.row_ptr, a.col_idx, static_cast<const VT *>(vals), static_cast<const X *>(x),
-                               static_cast<X *>(y), nrhs);
-            return hipGetLastError();
+        const int vx = vec_cols<X>(nrhs, {x, y});
+        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+            constexpr int VX = decltype(vc)::value;
+            return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
+                constexpr int RL = decltype(rc)::value;
+                hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, RL, VX>), dim3(a.nssr), dim3(block),
+                                   size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                   static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
+                                   a.nnz, nrhs);
+                return hipGetLastError();
+            });
         });
     });
 }
@@ -861,22 +1214,34 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
         using X = typename Store<VT>::X;
         using A = typename Store<VT>::A;
         const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
-        const int L = nrhs == 1 ? s.lanes_per_row : pow2_at_least(nrhs);
-        return by_lanes(L, [&](auto lc) -> hipError_t {
-            constexpr int LL = decltype(lc)::value;
-            const size_t lds = size_t(s.waves) * kAdjointLds;
-            if (ind)
-                hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, true>), dim3(a.nssr), dim3(block), lds, st, a.ssr_ptr,
-                                   a.sr_ptr, a.row_ptr, a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
-                                   static_cast<const X *>(x), static_cast<const X *>(g), static_cast<X *>(gx),
-                                   static_cast<A *>(gv), a.nnz, nrhs, int(a.sym));
-            else
-                hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, false>), dim3(a.nssr), dim3(block), lds, st, a.ssr_ptr,
-                                   a.sr_ptr, a.row_ptr, a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
-                                   static_cast<const X *>(x), static_cast<const X *>(g), static_cast<X *>(gx),
-                                   static_cast<A *>(gv), a.nnz, nrhs, int(a.sym));
-            return hipGetLastError();
-        });
+        auto launch = [&](auto indc) -> hipError_t {
+            constexpr bool IND = decltype(indc)::value;
+            if (nrhs == 1) {
+                return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
+                    constexpr int LL = decltype(lc)::value;
+                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(a.nssr), dim3(block),
+                                       size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                       a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
+                                       int(a.sym));
+                    return hipGetLastError();
+                });
+            }
+            const int vx = vec_cols<X>(nrhs, {x, g, gx});
+            return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+                constexpr int VX = decltype(vc)::value;
+                return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
+                    constexpr int RL = decltype(rc)::value;
+                    hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.nssr), dim3(block),
+                                       size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                       a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
+                                       nrhs);
+                    return hipGetLastError();
+                });
+            });
+        };
+        return ind ? launch(std::true_type{}) : launch(std::false_type{});
     });
 }
 
@@ -930,38 +1295,46 @@ hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtyp
 }
 
 hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, hipStream_t st) {
+                         Shape s, int grid, bool vec, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    const int R = pow2_at_least(nrhs);
     return by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
-        return by_lanes(nrhs == 1 ? s.lanes_per_row : R, [&](auto lc) -> hipError_t {
-            constexpr int LL = decltype(lc)::value;
-            hipLaunchKernelGGL((k_batch_forward<VT, LL, LL>), dim3(grid), dim3(block),
-                               nrhs == 1 ? size_t(s.waves) * kStageBytes : 0, st, descs, items, nitems, nrhs);
-            return hipGetLastError();
+        using X = typename Store<VT>::X;
+        const int vx = (nrhs > 1 && vec && nrhs % (16 / int(sizeof(X))) == 0) ? 16 / int(sizeof(X)) : 1;
+        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+            constexpr int VX = decltype(vc)::value;
+            return by_lanes(nrhs == 1 ? s.lanes_per_row : rhs_lanes(nrhs, VX), [&](auto lc) -> hipError_t {
+                constexpr int LL = decltype(lc)::value;
+                hipLaunchKernelGGL((k_batch_forward<VT, LL, VX>), dim3(grid), dim3(block), size_t(s.waves) * kBatchLds,
+                                   st, descs, items, nitems, nrhs);
+                return hipGetLastError();
+            });
         });
     });
 }
 
 hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, hipStream_t st) {
+                         Shape s, int grid, bool ind, bool vec, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    const int R = pow2_at_least(nrhs);
     return by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
-        return by_lanes(nrhs == 1 ? s.lanes_per_row : R, [&](auto lc) -> hipError_t {
-            constexpr int LL = decltype(lc)::value;
-            const size_t lds = size_t(s.waves) * kAdjointLds;
-            if (ind)
-                hipLaunchKernelGGL((k_batch_adjoint<VT, LL, true>), dim3(grid), dim3(block), lds, st, descs, items,
-                                   nitems, nrhs);
-            else
-                hipLaunchKernelGGL((k_batch_adjoint<VT, LL, false>), dim3(grid), dim3(block), lds, st, descs, items,
-                                   nitems, nrhs);
-            return hipGetLastError();
+        using X = typename Store<VT>::X;
+        const int vx = (nrhs > 1 && vec && nrhs % (16 / int(sizeof(X))) == 0) ? 16 / int(sizeof(X)) : 1;
+        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+            constexpr int VX = decltype(vc)::value;
+            return by_lanes(nrhs == 1 ? s.lanes_per_row : rhs_lanes(nrhs, VX), [&](auto lc) -> hipError_t {
+                constexpr int LL = decltype(lc)::value;
+                const size_t lds = size_t(s.waves) * kBatchLds;
+                if (ind)
+                    hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, true>), dim3(grid), dim3(block), lds, st, descs,
+                                       items, nitems, nrhs);
+                else
+                    hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, false>), dim3(grid), dim3(block), lds, st, descs,
+                                       items, nitems, nrhs);
+                return hipGetLastError();
+            });
         });
     });
 }
@@ -969,16 +1342,14 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj) {
     int blocks = 1;
     const int block = s.waves * kWave;
-    const int R = pow2_at_least(nrhs);
+    const size_t lds = size_t(s.waves) * kBatchLds;
     const hipError_t e = by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
-        return by_lanes(nrhs == 1 ? s.lanes_per_row : R, [&](auto lc) -> hipError_t {
+        return by_lanes(nrhs == 1 ? s.lanes_per_row : pow2_at_least(nrhs), [&](auto lc) -> hipError_t {
             constexpr int LL = decltype(lc)::value;
-            if (adj)
-                return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, false>, block,
-                                                                    size_t(s.waves) * kAdjointLds);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, LL>, block,
-                                                                nrhs == 1 ? size_t(s.waves) * kStageBytes : 0);
+            if (adj) return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, 1, false>,
+                                                                         block, lds);
+            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, 1>, block, lds);
         });
     });
     return (e != hipSuccess || blocks < 1) ? 1 : blocks;

@@ -71,12 +71,13 @@ hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs
 hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtype store, hipStream_t st);
 
 // Batched persistent launches over `nitems` (matrix, super-super-row) items.
+// `vec`: every right-hand-side block pointer is 16-byte aligned.
 hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, hipStream_t st);
+                         Shape s, int grid, bool vec, hipStream_t st);
 // `ind`: the descriptors' vals are caller values in CSR-k order (reached
 // through t_src); otherwise they are the handles' transposed copies.
 hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, hipStream_t st);
+                         Shape s, int grid, bool ind, bool vec, hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint);

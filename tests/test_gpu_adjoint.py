@@ -209,3 +209,36 @@ def test_adjoint_deterministic():
     b = M.adjoint(x, g)
     torch.cuda.synchronize()
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("nrhs", [3, 8])
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
+    from gen import CsrInput
+    rng = np.random.default_rng(nrhs + 10 * symmetric)
+    n = 2500
+    dense_rows = set(range(0, n, 97))
+    ii, jj = [], []
+    for i in range(n):
+        k = 1500 if i in dense_rows else int(rng.integers(1, 8))
+        cols = rng.choice(n, size=k, replace=False)
+        ii.extend([i] * k)
+        jj.extend(cols.tolist())
+    ii, jj = np.array(ii), np.array(jj)
+    if symmetric:
+        ii, jj = np.concatenate([ii, jj]), np.concatenate([jj, ii])
+    key = np.unique(ii * n + jj)
+    ii, jj = key // n, key % n
+    rp = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(ii, minlength=n), out=rp[1:])
+    A = CsrInput("longsym" if symmetric else "long", n, rp.astype(np.int32), jj.astype(np.int32),
+                 rng.uniform(-1, 1, len(jj)).astype(np.float32).astype(np.float64), {})
+    X = rng.uniform(-1, 1, (n, nrhs)).astype(np.float32).astype(np.float64)
+    G = rng.uniform(-1, 1, (n, nrhs)).astype(np.float32).astype(np.float64)
+    say("adjoint mrhs long", nrhs, symmetric)
+    M = _build(A, "f32", params(16, 4))
+    gx, gv = _adjoint(M, X, G)
+    _check_grad_x(gx, A, G, "f32", False, f"mrhs long {nrhs} {symmetric}")
+    ref = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    scale = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+    assert np.all(np.abs(gv - ref) <= OP.gamma(nrhs, 2.0 ** -24) * scale)

@@ -234,3 +234,48 @@ def test_argument_errors():
     assert e.value.name == "CSRK_ERR_ARG"  # nrhs < 1
     with pytest.raises(TypeError):
         M.spmv(x.float())
+
+
+def _long_row_matrix(n=3000, long_len=2000, every=89, seed=3):
+    from gen import CsrInput
+    rng = np.random.default_rng(seed)
+    rows = [np.sort(rng.choice(n, size=(long_len if i % every == 0 else int(rng.integers(0, 9))), replace=False))
+            for i in range(n)]
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    return CsrInput("long", n, rp.astype(np.int32), np.concatenate(rows).astype(np.int32),
+                    rng.uniform(-1, 1, int(rp[-1])), {})
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [4, 8])
+def test_multi_rhs_long_rows(store, nrhs):
+    A = _long_row_matrix()
+    X = np.random.default_rng(nrhs).uniform(-1, 1, (A.n, nrhs))
+    if store != "f64":
+        X = X.astype(np.float32).astype(np.float64)
+    say("mrhs long rows", store, nrhs)
+    M = _build(A, store, params(16, 4))
+    Y, perm = _run(M, X)
+    check_forward(Y, A, X, perm, store, False, label=f"long mrhs {store} {nrhs}")
+
+
+def test_multi_rhs_misaligned_block_uses_scalar_columns():
+    A = random_sparse(1200, 6.0, seed=44)
+    X = np.random.default_rng(44).uniform(-1, 1, (A.n, 8)).astype(np.float32).astype(np.float64)
+    M = _build(A, "f32", params(16, 4))
+    perm = M.structure()["perm"]
+    # a block starting 4 bytes into an allocation: 16-byte column slices are not aligned
+    raw = torch.zeros(A.n * 8 + 1, dtype=torch.float32, device="cuda")
+    raw[1:] = to_dev(X[perm], torch.float32).reshape(-1)
+    xd = raw[1:].view(A.n, 8)
+    assert xd.data_ptr() % 16 != 0
+    yraw = torch.zeros(A.n * 8 + 1, dtype=torch.float32, device="cuda")
+    yd = yraw[1:].view(A.n, 8)
+    M.spmv(xd, yd)
+    torch.cuda.synchronize()
+    check_forward(yd.double().cpu().numpy(), A, X, perm, "f32", False, label="misaligned mrhs")
+    # the aligned launch gives the same numbers up to summation order (bitwise: same order)
+    y2 = M.spmv(to_dev(X[perm], torch.float32).contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(y2, yd)
