@@ -5,19 +5,27 @@ of matrices, keeps the best pair per matrix, and fits SSRS and SRS separately
 as a - b ln(rdensity) (logarithmic regression, each fitted independently), then
 rounds to nearest with halves up.  This module does the same on the GPU at
 hand: for each matrix it builds the CSR-k structure for every (SRS, SSRS) in
-the sweep, times the forward kernel for every (lanes per row, waves per
-workgroup) launch shape, and returns the best; ``fit`` turns the per-matrix
-optima into the model's constants.
+the sweep (host builds run in parallel threads), times the forward kernel for
+every (lanes per row, waves per workgroup) launch shape, and returns the best;
+``fit`` turns the per-matrix optima into the model's constants and
+``evaluate`` compares the model's pick with the sweep optimum.
 
 Timing follows the paper's methodology (Section 5.4): data resident on the GPU,
-kernel time only, the mean of repeated runs after warm-up runs.
+kernel time only, the mean of repeated back-to-back runs after warm-up runs.
+
+    python -m paper_2203_05096_amd.autotune --scale 1.0 --out results.json
 """
 
 from __future__ import annotations
 
+import argparse
+import concurrent.futures as cf
 import itertools
+import json
 import math
-from dataclasses import dataclass, field
+import sys
+import time
+from dataclasses import asdict, dataclass, field
 
 import numpy as np
 import torch
@@ -25,11 +33,12 @@ import torch
 from . import _capi as C
 from .matrix import CsrkMatrix
 
-# The paper's GPU sweep values {2^i, 1.5 * 2^i} (Section 4.1), extended upward for
-# wave64 super-rows; SSRS counts super-rows per workgroup.
-SRS_SWEEP = (8, 12, 16, 24, 32, 48, 64, 96, 128)
-SSRS_SWEEP = (2, 4, 6, 8, 12, 16, 24, 32)
-LANES_SWEEP = (1, 2, 4, 8)
+# Candidate sizes: the paper's {2^i, 1.5 * 2^i} pattern (Section 4.1), over the
+# range where a super-row fills a wavefront's staging window; SSRS counts
+# super-rows per workgroup.
+SRS_SWEEP = (16, 24, 32, 48, 64, 96, 128)
+SSRS_SWEEP = (2, 4, 8)
+LANES_SWEEP = (1, 2, 4)
 WAVES_SWEEP = (2, 4, 8)
 
 
@@ -80,8 +89,8 @@ def time_forward(M: CsrkMatrix, x: torch.Tensor, y: torch.Tensor, reps: int = 20
 
 def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes_list=LANES_SWEEP,
           waves_list=WAVES_SWEEP, reorder: str = "bandk", nrhs: int = 1, reps: int = 20, seed: int = 0,
-          name: str | None = None) -> SweepResult:
-    """Times every combination on matrix A (a gen.CsrInput-like object with row_ptr, col_idx, vals)."""
+          name: str | None = None, threads: int = 8) -> SweepResult:
+    """Times every combination on matrix A (an object with row_ptr, col_idx, vals)."""
     n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
     res = SweepResult(name or getattr(A, "name", "matrix"), n, nnz, nnz / max(n, 1))
     dt = torch.float64 if store == "f64" else torch.float32
@@ -89,14 +98,21 @@ def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes
     shape = (n,) if nrhs == 1 else (n, nrhs)
     x = torch.rand(shape, generator=g, device="cuda", dtype=dt) * 2 - 1
     y = torch.empty_like(x)
-    for srs, ssrs in itertools.product(srs_list, ssrs_list):
+
+    def build(sizes):
+        srs, ssrs = sizes
         p = {"k": 3, "srs": srs, "ssrs": ssrs, "lanes_per_row": lanes_list[0], "waves_per_wg": waves_list[0],
              "reorder": reorder}
-        M = CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store)
-        for lanes, waves in itertools.product(lanes_list, waves_list):
-            C.csrk_set_launch(M.handle, lanes, waves)
-            res.trials.append(Trial(srs, ssrs, lanes, waves, reorder, time_forward(M, x, y, reps)))
-        M.close()
+        return sizes, C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        for (srs, ssrs), h in ex.map(build, itertools.product(srs_list, ssrs_list)):
+            C.csrk_upload(h, store)
+            M = CsrkMatrix(h, store)
+            for lanes, waves in itertools.product(lanes_list, waves_list):
+                C.csrk_set_launch(M.handle, lanes, waves)
+                res.trials.append(Trial(srs, ssrs, lanes, waves, reorder, time_forward(M, x, y, reps)))
+            M.close()
     return res
 
 
@@ -119,3 +135,53 @@ def model_pick(a_b: tuple, r: float) -> int:
     """round-half-up(a - b ln r), clamped to >= 1 (the paper's rounding, Section 4.1)."""
     a, b = a_b
     return max(1, int(math.floor(a - b * math.log(r) + 0.5)))
+
+
+def nearest(v, grid):
+    return min(grid, key=lambda g: (abs(g - v), g))
+
+
+def evaluate(results, consts: dict) -> list:
+    """For each matrix: the model's (SRS, SSRS) snapped to the sweep grid, its best time over launch shapes,
+    and the ratio to the sweep optimum."""
+    out = []
+    for r in results:
+        srs_grid = sorted({t.srs for t in r.trials})
+        ssrs_grid = sorted({t.ssrs for t in r.trials})
+        srs = nearest(model_pick(consts["srs"], r.rdensity), srs_grid)
+        ssrs = nearest(model_pick(consts["ssrs"], r.rdensity), ssrs_grid)
+        pick = r.best_for(srs, ssrs)
+        out.append({"name": r.name, "rdensity": r.rdensity, "model_srs": srs, "model_ssrs": ssrs,
+                    "model_us": pick.us, "best": asdict(r.best), "ratio": pick.us / r.best.us})
+    return out
+
+
+def main(argv=None):
+    import os
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--scale", type=float, default=1.0, help="grid scale of the tuning suite")
+    ap.add_argument("--store", default="f64")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--threads", type=int, default=16)
+    args = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import gen
+    suite = gen.tuning_suite(scale=args.scale)
+    results = []
+    for A in suite:
+        t = time.time()
+        r = sweep(A, args.store, threads=args.threads)
+        results.append(r)
+        print(f"{A.name}: n={r.n} r={r.rdensity:.2f} best {asdict(r.best)} ({time.time() - t:.1f}s)", flush=True)
+    consts = fit(results)
+    ev = evaluate(results, consts)
+    report = {"store": args.store, "scale": args.scale, "fit": consts, "evaluation": ev,
+              "trials": {r.name: [asdict(t) for t in r.trials] for r in results}}
+    print(json.dumps({"fit": consts, "evaluation": ev}, indent=1), flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(report, f)
+
+
+if __name__ == "__main__":
+    main()

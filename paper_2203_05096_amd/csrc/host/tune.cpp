@@ -8,6 +8,7 @@
 // this library's fit of the same form for its gfx950 kernels (one
 // super-super-row per workgroup, one super-row per wavefront), refitted from
 // measured sweeps.
+#include <algorithm>
 #include <cmath>
 
 #include "host.hpp"
@@ -25,11 +26,13 @@ int case_of(double r) {
     return 4;
 }
 
-// MI355X fit of the same logarithmic form.  SRS (rows per super-row) is sized
-// so one super-row's nonzeros fill a wavefront's LDS staging window; SSRS
-// (super-rows per workgroup) keeps every wavefront of the workgroup busy.
-constexpr double kMiSsrsA = 4.0, kMiSsrsB = 0.0;
-constexpr double kMiSrsA = 133.0, kMiSrsB = 35.5;
+// MI355X fit of the same logarithmic form, from the autotuner's sweep of
+// SRS in {16..128} x SSRS in {2, 4, 8} x launch shapes over eight stencil
+// matrices with rdensity 5 to 26.5 (FP64, best of back-to-back runs): the
+// best SRS falls and the best SSRS rises with rdensity.  One super-row per
+// wavefront was best on every matrix, so the workgroup has SSRS wavefronts.
+constexpr double kMiSsrsA = 0.084, kMiSsrsB = -1.289;
+constexpr double kMiSrsA = 101.38, kMiSrsB = 22.71;
 
 int32_t clamp_size(int64_t v, int64_t hi) { return static_cast<int32_t>(std::max<int64_t>(1, std::min(v, hi))); }
 
@@ -75,17 +78,20 @@ csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
     case CSRK_MODEL_MI355X:
         ssrs = round_half_up(kMiSsrsA - kMiSsrsB * lr);
         srs = round_half_up(kMiSrsA - kMiSrsB * lr);
+        // The fit turns negative past rdensity ~87 (the paper flattens its own
+        // fits by hand there); keep a super-row at least half a staging window.
+        srs = std::max<int64_t>(srs, static_cast<int64_t>(std::ceil(256.0 / r)));
         break;
     default:
         return CSRK_ERR_ARG;
     }
-    p.ssrs = clamp_size(ssrs, INT32_MAX);
+    p.ssrs = clamp_size(ssrs, model == CSRK_MODEL_MI355X ? 16 : INT32_MAX);
     p.srs = clamp_size(srs, INT32_MAX);
     // Lanes that reduce one row: a row per lane while rows are short, wider
     // groups as rows lengthen (the paper switches to an in-row parallel kernel
-    // above 8 nonzeros per row, Section 3).
-    p.lanes_per_row = r <= 16 ? 1 : r <= 32 ? 2 : r <= 64 ? 4 : r <= 128 ? 8 : 16;
-    p.waves_per_wg = 4;
+    // above 8 nonzeros per row, Section 3; the sweep put the switch near 10).
+    p.lanes_per_row = r <= 10 ? 1 : r <= 16 ? 2 : r <= 48 ? 4 : r <= 96 ? 8 : 16;
+    p.waves_per_wg = model == CSRK_MODEL_MI355X ? p.ssrs : 4;
     *out = p;
     return CSRK_OK;
 }

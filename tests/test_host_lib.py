@@ -3,6 +3,7 @@
 These call only host entry points (no GPU needed).
 """
 
+import math
 import os
 
 import numpy as np
@@ -282,3 +283,31 @@ def test_upload_without_gpu_reports_device_error():
     with pytest.raises(C.CsrkError) as e:
         C.csrk_build(rp, ci, np.ones(len(ci)), _params(2, 2), "f64")
     assert e.value.name == "CSRK_ERR_DEVICE"
+
+
+def test_mi355x_model_shape():
+    import math
+    for r in (2.2, 4.9375, 6.953125, 8.19, 13.7, 26.46, 80.0, 300.0):
+        n = 10 ** 6
+        p = C.csrk_tune(n, int(round(r * n)), "mi355x")
+        srs = max(math.floor(101.38 - 22.71 * math.log(r) + 0.5), math.ceil(256.0 / r))
+        ssrs = min(16, max(1, math.floor(0.084 + 1.289 * math.log(r) + 0.5)))
+        assert (p["srs"], p["ssrs"], p["waves_per_wg"]) == (srs, ssrs, ssrs), r
+        assert p["lanes_per_row"] == (1 if r <= 10 else 2 if r <= 16 else 4 if r <= 48 else 8 if r <= 96 else 16)
+        assert p["reorder"] == 0 and p["k"] == 3
+
+
+def test_autotune_fit_and_evaluate():
+    from paper_2203_05096_amd import autotune as T
+    res = []
+    for name, r, srs, ssrs in (("a", 5.0, 64, 2), ("b", 10.0, 48, 3), ("c", 25.0, 32, 4)):
+        sr = T.SweepResult(name, 1000, int(1000 * r), r)
+        for s_ in (16, 32, 48, 64):
+            for ss in (2, 3, 4):
+                sr.trials.append(T.Trial(s_, ss, 1, ss, "bandk", 10.0 + abs(s_ - srs) + 5 * abs(ss - ssrs)))
+        res.append(sr)
+    f = T.fit(res)
+    a, b = f["srs"]
+    assert abs((a - b * math.log(5.0)) - 64) < 6 and b > 0
+    ev = T.evaluate(res, f)
+    assert all(e["ratio"] >= 1.0 for e in ev) and ev[0]["model_srs"] in (48, 64)
