@@ -12,6 +12,8 @@ every (lanes per row, waves per workgroup) launch shape, and returns the best;
 
 Timing follows the paper's methodology (Section 5.4): data resident on the GPU,
 kernel time only, the mean of repeated back-to-back runs after warm-up runs.
+The objective is the forward product alone (the paper's) or the forward plus
+its adjoint (this project's step).
 
     python -m paper_2203_05096_amd.autotune --scale 1.0 --out results.json
 """
@@ -33,13 +35,16 @@ import torch
 from . import _capi as C
 from .matrix import CsrkMatrix
 
-# Candidate sizes: the paper's {2^i, 1.5 * 2^i} pattern (Section 4.1), over the
-# range where a super-row fills a wavefront's staging window; SSRS counts
-# super-rows per workgroup.
+# Candidate sizes: the paper's {2^i, 1.5 * 2^i} pattern (Section 4.1) for SRS,
+# over the range where a super-row fills a wavefront's staging window.  SSRS
+# counts super-rows per workgroup and is swept over powers of two: with one
+# super-row per wavefront (waves = SSRS, the default launch) workgroups of 3
+# or 6 wavefronts measured 5-8% slower than 2 or 4 on every matrix of the
+# tuning suite.
 SRS_SWEEP = (16, 24, 32, 48, 64, 96, 128)
 SSRS_SWEEP = (2, 4, 8)
 LANES_SWEEP = (1, 2, 4)
-WAVES_SWEEP = (2, 4, 8)
+WAVES_SWEEP = None  # None: waves per workgroup = SSRS
 
 
 @dataclass
@@ -87,10 +92,33 @@ def time_forward(M: CsrkMatrix, x: torch.Tensor, y: torch.Tensor, reps: int = 20
     return a.elapsed_time(b) * 1e3 / reps
 
 
+def time_step(M: CsrkMatrix, x, g, y, gx, gv, reps: int = 20, warmup: int = 5) -> float:
+    """Mean event time (microseconds) of one forward launch followed by one adjoint launch."""
+    lib = C.lib()
+    h, st = M.handle, torch.cuda.current_stream().cuda_stream
+    px, pg, py, pgx, pgv = x.data_ptr(), g.data_ptr(), y.data_ptr(), gx.data_ptr(), gv.data_ptr()
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+
+    def once():
+        if lib.csrk_spmv(h, None, px, py, nrhs, st) or lib.csrk_spmv_adjoint(h, None, px, pg, pgx, pgv, nrhs, st):
+            raise RuntimeError(C.csrk_last_error_detail())
+    for _ in range(warmup):
+        once()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        once()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) * 1e3 / reps
+
+
 def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes_list=LANES_SWEEP,
-          waves_list=WAVES_SWEEP, reorder: str = "bandk", nrhs: int = 1, reps: int = 20, seed: int = 0,
-          name: str | None = None, threads: int = 8) -> SweepResult:
-    """Times every combination on matrix A (an object with row_ptr, col_idx, vals)."""
+          waves_list=WAVES_SWEEP, reorder: str = "bandk", nrhs: int = 1, reps: int = 40, seed: int = 0,
+          name: str | None = None, threads: int = 8, objective: str = "forward") -> SweepResult:
+    """Times every combination on matrix A (an object with row_ptr, col_idx, vals).  objective is
+    "forward" (the paper's) or "step" (forward + adjoint); waves_list None ties the waves per
+    workgroup to SSRS."""
     n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
     res = SweepResult(name or getattr(A, "name", "matrix"), n, nnz, nnz / max(n, 1))
     dt = torch.float64 if store == "f64" else torch.float32
@@ -98,20 +126,26 @@ def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes
     shape = (n,) if nrhs == 1 else (n, nrhs)
     x = torch.rand(shape, generator=g, device="cuda", dtype=dt) * 2 - 1
     y = torch.empty_like(x)
+    if objective == "step":
+        gvec = torch.rand(shape, generator=g, device="cuda", dtype=dt) * 2 - 1
+        gx = torch.empty_like(x)
+        gv = torch.empty(nnz, device="cuda", dtype=dt)
 
     def build(sizes):
         srs, ssrs = sizes
-        p = {"k": 3, "srs": srs, "ssrs": ssrs, "lanes_per_row": lanes_list[0], "waves_per_wg": waves_list[0],
-             "reorder": reorder}
+        p = {"k": 3, "srs": srs, "ssrs": ssrs, "lanes_per_row": lanes_list[0],
+             "waves_per_wg": min(ssrs, 16) if waves_list is None else waves_list[0], "reorder": reorder}
         return sizes, C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
 
     with cf.ThreadPoolExecutor(threads) as ex:
         for (srs, ssrs), h in ex.map(build, itertools.product(srs_list, ssrs_list)):
             C.csrk_upload(h, store)
             M = CsrkMatrix(h, store)
-            for lanes, waves in itertools.product(lanes_list, waves_list):
+            for lanes, waves in itertools.product(lanes_list, [min(ssrs, 16)] if waves_list is None else waves_list):
                 C.csrk_set_launch(M.handle, lanes, waves)
-                res.trials.append(Trial(srs, ssrs, lanes, waves, reorder, time_forward(M, x, y, reps)))
+                us = time_forward(M, x, y, reps) if objective == "forward" else \
+                    time_step(M, x, gvec, y, gx, gv, reps)
+                res.trials.append(Trial(srs, ssrs, lanes, waves, reorder, us))
             M.close()
     return res
 
@@ -137,23 +171,75 @@ def model_pick(a_b: tuple, r: float) -> int:
     return max(1, int(math.floor(a - b * math.log(r) + 0.5)))
 
 
+def nearest_pow2(v: int) -> int:
+    """Nearest power of two, ties toward the smaller (the MI355X model's SSRS snap)."""
+    if v <= 1:
+        return 1
+    lo = 1 << (int(v).bit_length() - 1)
+    return lo if v - lo <= 2 * lo - v else 2 * lo
+
+
+def lanes_rule(r: float) -> int:
+    """Lanes per row of the MI355X model: a row per lane for short rows, wider groups as rows lengthen."""
+    return 1 if r <= 6 else 2 if r <= 24 else 4 if r <= 48 else 8 if r <= 96 else 16
+
+
 def nearest(v, grid):
     return min(grid, key=lambda g: (abs(g - v), g))
 
 
 def evaluate(results, consts: dict) -> list:
-    """For each matrix: the model's (SRS, SSRS) snapped to the sweep grid, its best time over launch shapes,
-    and the ratio to the sweep optimum."""
+    """For each matrix: the model's shape (fitted SRS and power-of-two SSRS, snapped to the sweep grid; lanes
+    by rdensity; waves = SSRS), its time, and the ratio to the sweep optimum."""
     out = []
     for r in results:
         srs_grid = sorted({t.srs for t in r.trials})
         ssrs_grid = sorted({t.ssrs for t in r.trials})
+        lanes_grid = sorted({t.lanes for t in r.trials})
         srs = nearest(model_pick(consts["srs"], r.rdensity), srs_grid)
-        ssrs = nearest(model_pick(consts["ssrs"], r.rdensity), ssrs_grid)
-        pick = r.best_for(srs, ssrs)
+        ssrs = nearest(nearest_pow2(model_pick(consts["ssrs"], r.rdensity)), ssrs_grid)
+        lanes = nearest(lanes_rule(r.rdensity), lanes_grid)
+        same = [t for t in r.trials if (t.srs, t.ssrs, t.lanes) == (srs, ssrs, lanes)]
+        pick = min(same, key=lambda t: t.us) if same else r.best_for(srs, ssrs)
         out.append({"name": r.name, "rdensity": r.rdensity, "model_srs": srs, "model_ssrs": ssrs,
-                    "model_us": pick.us, "best": asdict(r.best), "ratio": pick.us / r.best.us})
+                    "model_lanes": pick.lanes, "model_us": pick.us, "best": asdict(r.best),
+                    "ratio": pick.us / r.best.us})
     return out
+
+
+def load(path: str) -> list:
+    """Sweep results from a report written by ``--out``."""
+    with open(path) as f:
+        rep = json.load(f)
+    pts = {p[0]: p for p in rep["fit"]["points"]}
+    out = []
+    for name, trials in rep["trials"].items():
+        ts = [Trial(**t) for t in trials]
+        n = next((e for e in rep["evaluation"] if e["name"] == name), None)
+        res = SweepResult(name, 0, 0, pts[name][1] if name in pts else n["rdensity"])
+        res.trials = ts
+        out.append(res)
+    return out
+
+
+def markdown(groups: dict, consts: dict, command: str) -> str:
+    """A summary table per storage type: best shape, model shape, ratio."""
+    a_r, b_r = consts["srs"]
+    a_s, b_s = consts["ssrs"]
+    lines = [f"Fit (Section 4.1 form, each size regressed on ln r separately, over all sweeps below): "
+             f"SRS = {a_r:.2f} - {b_r:.2f} ln r; SSRS = {a_s:.3f} - ({b_s:.4f}) ln r, rounded half up, then "
+             f"snapped to the nearest power of two.", "", "Command:", "", "    " + command, ""]
+    for store, results in groups.items():
+        lines += [f"### {store}", "",
+                  "| matrix | rdensity | best (SRS, SSRS, lanes) | best us | model (SRS, SSRS, lanes) | model us |"
+                  " model / best |", "|---|---|---|---|---|---|---|"]
+        for e in evaluate(results, consts):
+            b = e["best"]
+            lines.append(f"| {e['name']} | {e['rdensity']:.2f} | ({b['srs']}, {b['ssrs']}, {b['lanes']}) | "
+                         f"{b['us']:.1f} | ({e['model_srs']}, {e['model_ssrs']}, {e['model_lanes']}) | "
+                         f"{e['model_us']:.1f} | {e['ratio']:.3f} |")
+        lines.append("")
+    return "\n".join(lines)
 
 
 def main(argv=None):
@@ -163,19 +249,37 @@ def main(argv=None):
     ap.add_argument("--store", default="f64")
     ap.add_argument("--out", default=None)
     ap.add_argument("--threads", type=int, default=16)
+    ap.add_argument("--objective", choices=["forward", "step"], default="step")
+    ap.add_argument("--from-json", nargs="+", default=None,
+                    help="fit and evaluate earlier --out reports together instead of sweeping")
+    ap.add_argument("--markdown", default=None, help="with --from-json: write a summary table here")
     args = ap.parse_args(argv)
+    if args.from_json:
+        groups = {}
+        for p in args.from_json:
+            with open(p) as f:
+                store = json.load(f).get("store", p)
+            groups[f"{store} ({os.path.basename(p)})"] = load(p)
+        consts = fit([r for g in groups.values() for r in g])
+        text = markdown(groups, consts, "python -m paper_2203_05096_amd.autotune --from-json " +
+                        " ".join(args.from_json))
+        print(text)
+        if args.markdown:
+            with open(args.markdown, "w") as f:
+                f.write(text + "\n")
+        return
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import gen
     suite = gen.tuning_suite(scale=args.scale)
     results = []
     for A in suite:
         t = time.time()
-        r = sweep(A, args.store, threads=args.threads)
+        r = sweep(A, args.store, threads=args.threads, objective=args.objective)
         results.append(r)
         print(f"{A.name}: n={r.n} r={r.rdensity:.2f} best {asdict(r.best)} ({time.time() - t:.1f}s)", flush=True)
     consts = fit(results)
     ev = evaluate(results, consts)
-    report = {"store": args.store, "scale": args.scale, "fit": consts, "evaluation": ev,
+    report = {"store": args.store, "scale": args.scale, "objective": args.objective, "fit": consts, "evaluation": ev,
               "trials": {r.name: [asdict(t) for t in r.trials] for r in results}}
     print(json.dumps({"fit": consts, "evaluation": ev}, indent=1), flush=True)
     if args.out:

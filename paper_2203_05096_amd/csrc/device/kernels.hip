@@ -89,6 +89,11 @@ __device__ __forceinline__ T group_sum(T v) {
 // V consecutive column indices starting at pos (pos % V == 0) and the values
 // of those entries: vals[pos + e], or vals[src[pos + e]] when the values are
 // reached through an index map (IND).  Entries at or beyond nnz read as 0.
+// The value stream is read with non-temporal loads: each value is used once
+// per product, and keeping it out of the caches leaves the Infinity Cache to
+// col_idx, row_ptr and the vectors, which the forward and the adjoint of a
+// step share (measured: the forward + adjoint step on a 128^3 7-point matrix
+// runs about 4% faster; loading col_idx the same way made it slower).
 template <typename VT, bool IND>
 __device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int32_t *__restrict__ cols,
                                          const int32_t *__restrict__ src, int64_t pos, int64_t nnz,
@@ -106,7 +111,7 @@ __device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int3
             }
         } else {
             typedef VT VV __attribute__((ext_vector_type(V)));
-            const VV vv = *reinterpret_cast<const VV *>(vals + pos);
+            const VV vv = __builtin_nontemporal_load(reinterpret_cast<const VV *>(vals + pos));
 #pragma unroll
             for (int e = 0; e < V; ++e) {
                 c[e] = cv[e];

@@ -27,12 +27,23 @@ int case_of(double r) {
 }
 
 // MI355X fit of the same logarithmic form, from the autotuner's sweep of
-// SRS in {16..128} x SSRS in {2, 4, 8} x launch shapes over eight stencil
-// matrices with rdensity 5 to 26.5 (FP64, best of back-to-back runs): the
-// best SRS falls and the best SSRS rises with rdensity.  One super-row per
-// wavefront was best on every matrix, so the workgroup has SSRS wavefronts.
-constexpr double kMiSsrsA = 0.084, kMiSsrsB = -1.289;
-constexpr double kMiSrsA = 101.38, kMiSrsB = 22.71;
+// SRS in {16..128} x SSRS in {2, 4, 8} x lanes per row in {1, 2, 4} over
+// eight stencil matrices with rdensity 5 to 26.5, FP64 and FP32 storage,
+// timing the forward product followed by its adjoint.  The best SRS falls
+// with rdensity; the best SSRS shows no trend (the fit is flat near 2).  One
+// super-row per wavefront was best on every matrix, so a workgroup has SSRS
+// wavefronts, and SSRS is snapped to a power of two (workgroups of 3 or 6
+// wavefronts measured 5-8% slower).
+constexpr double kMiSsrsA = 2.294, kMiSsrsB = -0.0357;
+constexpr double kMiSrsA = 124.21, kMiSrsB = 32.80;
+
+// Nearest power of two, ties toward the smaller.
+int64_t nearest_pow2(int64_t v) {
+    if (v <= 1) return 1;
+    int64_t lo = 1;
+    while (lo * 2 <= v) lo *= 2;
+    return (v - lo <= 2 * lo - v) ? lo : 2 * lo;
+}
 
 int32_t clamp_size(int64_t v, int64_t hi) { return static_cast<int32_t>(std::max<int64_t>(1, std::min(v, hi))); }
 
@@ -76,7 +87,7 @@ csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
         }
         break;
     case CSRK_MODEL_MI355X:
-        ssrs = round_half_up(kMiSsrsA - kMiSsrsB * lr);
+        ssrs = nearest_pow2(round_half_up(kMiSsrsA - kMiSsrsB * lr));
         srs = round_half_up(kMiSrsA - kMiSrsB * lr);
         // The fit turns negative past rdensity ~87 (the paper flattens its own
         // fits by hand there); keep a super-row at least half a staging window.
@@ -89,8 +100,9 @@ csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
     p.srs = clamp_size(srs, INT32_MAX);
     // Lanes that reduce one row: a row per lane while rows are short, wider
     // groups as rows lengthen (the paper switches to an in-row parallel kernel
-    // above 8 nonzeros per row, Section 3; the sweep put the switch near 10).
-    p.lanes_per_row = r <= 10 ? 1 : r <= 16 ? 2 : r <= 48 ? 4 : r <= 96 ? 8 : 16;
+    // above 8 nonzeros per row, Section 3; the sweep put the switches near 6
+    // and 24).
+    p.lanes_per_row = r <= 6 ? 1 : r <= 24 ? 2 : r <= 48 ? 4 : r <= 96 ? 8 : 16;
     p.waves_per_wg = model == CSRK_MODEL_MI355X ? p.ssrs : 4;
     *out = p;
     return CSRK_OK;

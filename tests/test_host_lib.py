@@ -287,13 +287,12 @@ def test_upload_without_gpu_reports_device_error():
 
 def test_mi355x_model_shape():
     import math
-    for r in (2.2, 4.9375, 6.953125, 8.19, 13.7, 26.46, 80.0, 300.0):
+    for r in (1.0, 2.2, 4.9375, 6.953125, 8.19, 13.7, 26.46, 80.0, 300.0, 1000.0):
         n = 10 ** 6
         p = C.csrk_tune(n, int(round(r * n)), "mi355x")
-        srs = max(math.floor(101.38 - 22.71 * math.log(r) + 0.5), math.ceil(256.0 / r))
-        ssrs = min(16, max(1, math.floor(0.084 + 1.289 * math.log(r) + 0.5)))
-        assert (p["srs"], p["ssrs"], p["waves_per_wg"]) == (srs, ssrs, ssrs), r
-        assert p["lanes_per_row"] == (1 if r <= 10 else 2 if r <= 16 else 4 if r <= 48 else 8 if r <= 96 else 16)
+        srs = max(math.floor(124.21 - 32.80 * math.log(r) + 0.5), math.ceil(256.0 / r))
+        assert (p["srs"], p["ssrs"], p["waves_per_wg"]) == (srs, 2, 2), r
+        assert p["lanes_per_row"] == (1 if r <= 6 else 2 if r <= 24 else 4 if r <= 48 else 8 if r <= 96 else 16)
         assert p["reorder"] == 0 and p["k"] == 3
 
 
@@ -311,3 +310,14 @@ def test_autotune_fit_and_evaluate():
     assert abs((a - b * math.log(5.0)) - 64) < 6 and b > 0
     ev = T.evaluate(res, f)
     assert all(e["ratio"] >= 1.0 for e in ev) and ev[0]["model_srs"] in (48, 64)
+    assert all(e["model_ssrs"] in (2, 4) for e in ev)
+
+
+def test_autotune_helpers_match_library_model():
+    from paper_2203_05096_amd import autotune as T
+    assert [T.nearest_pow2(v) for v in range(0, 13)] == [1, 1, 2, 2, 4, 4, 4, 8, 8, 8, 8, 8, 8]
+    assert T.nearest_pow2(24) == 16 and T.nearest_pow2(25) == 32
+    for r in (1.0, 5.0, 6.0, 6.01, 13.7, 24.0, 24.5, 48.0, 60.0, 96.0, 97.0, 400.0):
+        n = 100000
+        p = C.csrk_tune(n, int(round(r * n)), "mi355x")
+        assert p["lanes_per_row"] == T.lanes_rule(int(round(r * n)) / n), r
