@@ -90,6 +90,9 @@ typedef struct csrk_info {
     int32_t max_ssr_rows;     /* largest row count of a super-super-row */
     int32_t on_device;        /* 1 when device arrays exist */
     int32_t store;            /* csrk_dtype of the device values (valid when on_device) */
+    int32_t long_rows;        /* rows with more than 1024 nonzeros: each is computed by a
+                                 workgroup of its own (Section 5.5 names splitting dense
+                                 rows as the fix for irregular matrices) */
     csrk_params params;
 } csrk_info;
 

@@ -179,6 +179,14 @@ def nearest_pow2(v: int) -> int:
     return lo if v - lo <= 2 * lo - v else 2 * lo
 
 
+def snap_srs(v: int, floor: int = 1) -> int:
+    """Nearest size of the {2^i, 3 * 2^(i-1)} set (ties toward the smaller), at least ``floor``: the MI355X
+    model's SRS snap."""
+    cands = sorted({c for i in range(41) for c in (1 << i, 3 * (1 << i) // 2)})
+    best = min(cands, key=lambda c: (abs(c - v), c))
+    return best if best >= floor else next(c for c in cands if c >= floor)
+
+
 def lanes_rule(r: float) -> int:
     """Lanes per row of the MI355X model: a row per lane for short rows, wider groups as rows lengthen."""
     return 1 if r <= 6 else 2 if r <= 24 else 4 if r <= 48 else 8 if r <= 96 else 16
@@ -189,14 +197,14 @@ def nearest(v, grid):
 
 
 def evaluate(results, consts: dict) -> list:
-    """For each matrix: the model's shape (fitted SRS and power-of-two SSRS, snapped to the sweep grid; lanes
-    by rdensity; waves = SSRS), its time, and the ratio to the sweep optimum."""
+    """For each matrix: the model's shape (fitted SRS snapped onto the size set, power-of-two SSRS, both then
+    matched to the sweep grid; lanes by rdensity; waves = SSRS), its time, and the ratio to the sweep optimum."""
     out = []
     for r in results:
         srs_grid = sorted({t.srs for t in r.trials})
         ssrs_grid = sorted({t.ssrs for t in r.trials})
         lanes_grid = sorted({t.lanes for t in r.trials})
-        srs = nearest(model_pick(consts["srs"], r.rdensity), srs_grid)
+        srs = nearest(snap_srs(model_pick(consts["srs"], r.rdensity), math.ceil(256.0 / r.rdensity)), srs_grid)
         ssrs = nearest(nearest_pow2(model_pick(consts["ssrs"], r.rdensity)), ssrs_grid)
         lanes = nearest(lanes_rule(r.rdensity), lanes_grid)
         same = [t for t in r.trials if (t.srs, t.ssrs, t.lanes) == (srs, ssrs, lanes)]

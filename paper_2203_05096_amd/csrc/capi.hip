@@ -35,6 +35,9 @@ struct csrk_matrix {
     int32_t *d_t_row_ptr = nullptr, *d_t_col = nullptr, *d_t_src = nullptr;  // t_row_ptr/t_col only if nonsymmetric
     void *d_vals = nullptr;
     void *d_vals_t = nullptr;  // stored values in A'^T order, for the adjoint
+    // rows of A' / A'^T longer than csrk::dev::kLongRow (t_ only if nonsymmetric)
+    std::vector<int32_t> long_rows, t_long_rows;
+    int32_t *d_long = nullptr, *d_t_long = nullptr;
 };
 
 struct csrk_batch_s {
@@ -101,10 +104,11 @@ void free_device(csrk_matrix *h) {
     DeviceScope ds(h->device);
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
                     (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
-                    h->d_vals_t})
+                    h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long})
         if (p) (void)hipFree(p);
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
     h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
+    h->d_long = h->d_t_long = nullptr;
     h->d_vals = h->d_vals_t = nullptr;
     h->on_device = false;
 }
@@ -176,7 +180,19 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.t_src = h->d_t_src;
     a.vals_t = h->d_vals_t;
     a.sym = sym;
+    a.long_rows = h->d_long;
+    a.nlong = static_cast<int32_t>(h->long_rows.size());
+    a.t_long_rows = sym ? h->d_long : h->d_t_long;
+    a.t_nlong = static_cast<int32_t>(sym ? h->long_rows.size() : h->t_long_rows.size());
     return a;
+}
+
+// Rows whose length (from a row pointer array) exceeds kLongRow, ascending.
+std::vector<int32_t> long_rows_of(const std::vector<int32_t> &rp) {
+    std::vector<int32_t> out;
+    for (size_t i = 0; i + 1 < rp.size(); ++i)
+        if (rp[i + 1] - rp[i] > csrk::dev::kLongRow) out.push_back(static_cast<int32_t>(i));
+    return out;
 }
 
 void need_device(const csrk_matrix *h) {
@@ -322,6 +338,10 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
                 h->d_t_row_ptr = upload_array(h->trans.t_row_ptr, "transposed row_ptr");
                 h->d_t_col = upload_array(h->trans.t_col, "transposed col_idx");
             }
+            h->long_rows = long_rows_of(h->row_ptr);
+            h->t_long_rows = h->trans.symmetric ? std::vector<int32_t>() : long_rows_of(h->trans.t_row_ptr);
+            if (!h->long_rows.empty()) h->d_long = upload_array(h->long_rows, "long rows");
+            if (!h->t_long_rows.empty()) h->d_t_long = upload_array(h->t_long_rows, "transposed long rows");
             hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
             hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
             h->on_device = true;
@@ -387,6 +407,7 @@ csrk_status csrk_get_info(csrk_handle h, csrk_info *out) {
         i.max_ssr_rows = h->max_ssr_rows;
         i.on_device = h->on_device ? 1 : 0;
         i.store = h->store;
+        i.long_rows = static_cast<int32_t>(long_rows_of(h->row_ptr).size());
         i.params = h->params;
         *out = i;
         return CSRK_OK;

@@ -128,10 +128,201 @@ __device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int3
     }
 }
 
+// ------------------------------------------------------------------ rows longer than a window
+//
+// A row with more nonzeros than a staging window is streamed in windows of
+// kStageEntries entries by one wavefront: every lane issues all its 16-byte
+// loads of a window before the dependent gathers, as in the windowed path, and
+// keeps a running partial sum; the lanes are summed at the end.  Rows longer
+// than kLongRow are not left to one wavefront at all: they are listed at
+// upload and split over the 16 wavefronts of a workgroup of their own
+// (k_long_forward / k_long_adjoint), which the paper names as the way to stop
+// very dense rows from being computed serially (Section 5.5).
+
+// Sum over entries [k0, k1) of value(k) * x[col(k)] (value(k) = vals[k], or
+// vals[src[k]] with IND) by one wavefront; every lane returns the sum.
+template <typename VT, bool IND>
+__device__ __forceinline__ typename Store<VT>::A range_dot(int64_t k0, int64_t k1, const int32_t *__restrict__ cols,
+                                                           const int32_t *__restrict__ src,
+                                                           const VT *__restrict__ vals,
+                                                           const typename Store<VT>::X *__restrict__ x, int64_t nnz,
+                                                           int lane) {
+    using A = typename Store<VT>::A;
+    constexpr int V = Store<VT>::V;
+    constexpr int U = kStageEntries / (kWave * V);
+    A acc = 0;
+    for (int64_t w0 = k0 & ~int64_t(V - 1); w0 < k1; w0 += kStageEntries) {
+        const int64_t base = w0 + int64_t(lane) * V;
+        A v[U][V];
+        int32_t c[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < k1) {
+                load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
+            }
+        }
+        A xv[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                xv[u][e] = (k >= k0 && k < k1) ? A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                if (k >= k0 && k < k1) acc += v[u][e] * xv[u][e];
+            }
+    }
+    return group_sum<kWave>(acc);
+}
+
+// grad_vals[k] = gi * x[cols[k]] over entries [k0, k1) of one row, by one
+// wavefront: 16-byte column loads, then the gathers, then 16-byte stores.
+template <typename VT>
+__device__ __forceinline__ void range_grad_vals(int64_t k0, int64_t k1, typename Store<VT>::A gi,
+                                                const int32_t *__restrict__ cols,
+                                                const typename Store<VT>::X *__restrict__ x,
+                                                typename Store<VT>::A *__restrict__ gv, int64_t nnz, int lane) {
+    using A = typename Store<VT>::A;
+    constexpr int VA = 16 / int(sizeof(A));
+    constexpr int U = kStageEntries / (kWave * VA);
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    typedef int32_t CV __attribute__((ext_vector_type(VA)));
+    for (int64_t w0 = k0 & ~int64_t(VA - 1); w0 < k1; w0 += kStageEntries) {
+        const int64_t base = w0 + int64_t(lane) * VA;
+        int32_t c[U][VA];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * VA;
+            if (pos < k1 && pos + VA <= nnz) {
+                const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[u][e] = cv[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) c[u][e] = (pos < k1 && pos + e < nnz) ? cols[pos + e] : 0;
+            }
+        }
+        A out[U][VA];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < VA; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * VA + e;
+                out[u][e] = (k >= k0 && k < k1) ? gi * A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * VA;
+            if (pos >= k0 && pos + VA <= k1) {
+                AV ov;
+#pragma unroll
+                for (int e = 0; e < VA; ++e) ov[e] = out[u][e];
+                *reinterpret_cast<AV *>(gv + pos) = ov;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VA; ++e) {
+                    const int64_t k = pos + e;
+                    if (k >= k0 && k < k1) gv[k] = out[u][e];
+                }
+            }
+        }
+    }
+}
+
+// Both gradients over entries [k0, k1) of row i of a symmetric pattern, by one
+// wavefront: grad_vals[k] = gi * x[cols[k]] and the returned sum of
+// valueT(k) * g[cols[k]] (a part of grad_x[i]); every lane returns the sum.
+template <typename VT, bool IND>
+__device__ __forceinline__ typename Store<VT>::A range_adjoint(int64_t k0, int64_t k1, typename Store<VT>::A gi,
+                                                               const int32_t *__restrict__ cols,
+                                                               const int32_t *__restrict__ src,
+                                                               const VT *__restrict__ valsT,
+                                                               const typename Store<VT>::X *__restrict__ x,
+                                                               const typename Store<VT>::X *__restrict__ g,
+                                                               typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                               int lane) {
+    using A = typename Store<VT>::A;
+    constexpr int V = Store<VT>::V;
+    constexpr int U = kStageEntries / (kWave * V);
+    typedef A AV __attribute__((ext_vector_type(V)));
+    A acc = 0;
+    for (int64_t w0 = k0 & ~int64_t(V - 1); w0 < k1; w0 += kStageEntries) {
+        const int64_t base = w0 + int64_t(lane) * V;
+        A v[U][V];
+        int32_t c[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < k1) {
+                load_vec<VT, IND>(valsT, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
+            }
+        }
+        A xs[U][V], gs[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                xs[u][e] = (k >= k0 && k < k1) ? A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                gs[u][e] = (k >= k0 && k < k1) ? A(g[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            A gvv[V];
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = pos + e;
+                const bool ok = k >= k0 && k < k1;
+                gvv[e] = ok ? gi * xs[u][e] : A(0);
+                if (ok) acc += v[u][e] * gs[u][e];
+            }
+            if (pos >= k0 && pos + V <= k1) {
+                AV ov;
+#pragma unroll
+                for (int e = 0; e < V; ++e) ov[e] = gvv[e];
+                *reinterpret_cast<AV *>(gv + pos) = ov;
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int64_t k = pos + e;
+                    if (k >= k0 && k < k1) gv[k] = gvv[e];
+                }
+            }
+        }
+    }
+    return group_sum<kWave>(acc);
+}
+
 // ------------------------------------------------------------------ forward
 
 // y[r0..r1) = rows r0..r1-1 of (values) * x, one super-row, single right-hand
-// side.  The wavefront walks the super-row in windows of at most 64 whole
+// side; with skip_long, rows longer than kLongRow are left out (their own
+// kernel computes them).  The wavefront walks the super-row in windows of at most 64 whole
 // rows whose nonzeros fit its LDS staging area.  Per window: every lane issues
 // all its 16-byte loads of col_idx / values for the whole window before the
 // dependent x gathers; the row ends of the next window are fetched meanwhile;
@@ -141,7 +332,7 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
                                            const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
                                            const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                            typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                           typename Store<VT>::A *__restrict__ buf, int lane) {
+                                           typename Store<VT>::A *__restrict__ buf, int lane, bool skip_long) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
@@ -158,13 +349,13 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
         const uint64_t mask = __ballot(fits);
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
-            // Row ra alone exceeds the staging window: sum it straight from memory.
+            // Row ra alone exceeds the staging window: stream it in windows, or
+            // leave it to the long-row kernel.
             const int32_t re = uniform(__shfl(my_end, 0));
-            A acc = 0;
-            for (int64_t k = int64_t(cs) + lane; k < re; k += kWave)
-                acc += Store<VT>::widen(vals[IND ? src[k] : k]) * A(x[cols[k]]);
-            acc = group_sum<kWave>(acc);
-            if (lane == 0) y[ra] = X(acc);
+            if (!(skip_long && re - cs > kLongRow)) {
+                const A acc = range_dot<VT, IND>(cs, re, cols, src, vals, x, nnz, lane);
+                if (lane == 0) y[ra] = X(acc);
+            }
             cs = re;
             ++ra;
             my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
@@ -229,7 +420,8 @@ template <typename VT, int L>
 __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
-                                                    typename Store<VT>::X *__restrict__ y, int64_t nnz) {
+                                                    typename Store<VT>::X *__restrict__ y, int64_t nnz,
+                                                    int skip_long) {
     using A = typename Store<VT>::A;
     constexpr int CAP = kStageEntries;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -241,7 +433,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_forward<VT, L, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y, nnz,
-                                 buf, lane);
+                                 buf, lane, skip_long != 0);
 }
 
 // LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
@@ -460,7 +652,7 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
                                              const typename Store<VT>::X *__restrict__ x,
                                              const typename Store<VT>::X *__restrict__ g,
                                              typename Store<VT>::A *__restrict__ gv, int64_t nnz,
-                                             unsigned char *__restrict__ lds, int lane) {
+                                             unsigned char *__restrict__ lds, int lane, bool skip_long) {
     using A = typename Store<VT>::A;
     constexpr int VA = 16 / int(sizeof(A));  // grad_vals entries per 16-byte store
     constexpr int CAP = kStageEntries;
@@ -481,8 +673,7 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
             const int32_t re = uniform(__shfl(my_end, 0));
-            const A gi = A(g[ra]);
-            for (int64_t k = int64_t(cs) + lane; k < re; k += kWave) gv[k] = gi * A(x[cols[k]]);
+            if (!(skip_long && re - cs > kLongRow)) range_grad_vals<VT>(cs, re, A(g[ra]), cols, x, gv, nnz, lane);
             cs = re;
             ++ra;
             my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
@@ -708,7 +899,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
                                                  const typename Store<VT>::X *__restrict__ g,
                                                  typename Store<VT>::X *__restrict__ gx,
                                                  typename Store<VT>::A *__restrict__ gv, int64_t nnz,
-                                                 unsigned char *__restrict__ lds, int lane) {
+                                                 unsigned char *__restrict__ lds, int lane, bool skip_long) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
@@ -728,17 +919,13 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
         const uint64_t mask = __ballot(fits);
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
-            // Row ra alone exceeds the staging window: both gradients straight from memory.
+            // Row ra alone exceeds the staging window: stream it in windows, or
+            // leave it to the long-row kernel.
             const int32_t re = uniform(__shfl(my_end, 0));
-            const A gi = A(g[ra]);
-            A acc = 0;
-            for (int64_t k = int64_t(cs) + lane; k < re; k += kWave) {
-                const int32_t j = cols[k];
-                gv[k] = gi * A(x[j]);
-                acc += Store<VT>::widen(valsT[IND ? src[k] : k]) * A(g[j]);
+            if (!(skip_long && re - cs > kLongRow)) {
+                const A acc = range_adjoint<VT, IND>(cs, re, A(g[ra]), cols, src, valsT, x, g, gv, nnz, lane);
+                if (lane == 0) gx[ra] = X(acc);
             }
-            acc = group_sum<kWave>(acc);
-            if (lane == 0) gx[ra] = X(acc);
             cs = re;
             ++ra;
             my_end = (ra + lane < r1) ? row_ptr[ra + lane + 1] : 0;
@@ -845,15 +1032,16 @@ __device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t
                                            const typename Store<VT>::X *__restrict__ g,
                                            typename Store<VT>::X *__restrict__ gx,
                                            typename Store<VT>::A *__restrict__ gv, int64_t nnz, bool sym,
-                                           unsigned char *__restrict__ lds, int lane) {
+                                           unsigned char *__restrict__ lds, int lane, bool skip_long) {
     using A = typename Store<VT>::A;
     if (sym && gx && gv) {
-        sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane);
+        sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane, skip_long);
         return;
     }
-    if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane);
+    if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, skip_long);
     if (gx)
-        sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, reinterpret_cast<A *>(lds), lane);
+        sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, reinterpret_cast<A *>(lds), lane,
+                               skip_long);
 }
 
 // Both gradients of one super-row, several right-hand sides (RL lanes x VX columns per row).
@@ -887,7 +1075,8 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
                                                        const typename Store<VT>::X *__restrict__ x,
                                                        const typename Store<VT>::X *__restrict__ g,
                                                        typename Store<VT>::X *__restrict__ gx,
-                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym) {
+                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym,
+                                                       int skip_long) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
@@ -897,7 +1086,7 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
-                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane);
+                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane, skip_long != 0);
 }
 
 template <typename VT, int RL, int VX, bool IND>
@@ -917,6 +1106,86 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
                                          t_src, valsT, x, g, gx, gv, nnz, nrhs, lds, lane);
+}
+
+// ------------------------------------------------------------------ long rows
+//
+// One workgroup of kLongWaves wavefronts per listed row: wavefront w takes the
+// w-th of kLongWaves contiguous slices of the row (slice lengths a multiple of
+// the 16-byte load width), and the slices' sums are added in slice order, so
+// results do not depend on timing.
+
+template <int V>
+__device__ __forceinline__ void long_slice(int64_t k0, int64_t k1, int wave, int64_t &a, int64_t &b) {
+    const int64_t per = ((k1 - k0 + kLongWaves - 1) / kLongWaves + V - 1) / V * V;
+    a = min(k1, k0 + int64_t(wave) * per);
+    b = min(k1, a + per);
+}
+
+template <typename VT>
+__global__ void __launch_bounds__(kLongWaves * kWave) k_long_forward(const int32_t *__restrict__ rows,
+                                                                     const int32_t *__restrict__ row_ptr,
+                                                                     const int32_t *__restrict__ cols,
+                                                                     const VT *__restrict__ vals,
+                                                                     const typename Store<VT>::X *__restrict__ x,
+                                                                     typename Store<VT>::X *__restrict__ y,
+                                                                     int64_t nnz) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    __shared__ A part[kLongWaves];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const int32_t r = rows[blockIdx.x];
+    int64_t a, b;
+    long_slice<Store<VT>::V>(row_ptr[r], row_ptr[r + 1], wave, a, b);
+    const A sum = (a < b) ? range_dot<VT, false>(a, b, cols, nullptr, vals, x, nnz, lane) : A(0);
+    if (lane == 0) part[wave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A t = 0;
+        for (int w = 0; w < kLongWaves; ++w) t += part[w];
+        y[r] = X(t);
+    }
+}
+
+// Items [0, na) are long rows of A' (rows): grad_vals of the row, plus grad_x
+// of the same row when `fused` (symmetric pattern, both outputs).  Items
+// [na, grid) are long rows of A'^T (t_rows): grad_x only.
+template <typename VT, bool IND>
+__global__ void __launch_bounds__(kLongWaves * kWave) k_long_adjoint(
+    const int32_t *__restrict__ rows, int32_t na, const int32_t *__restrict__ t_rows, int fused,
+    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr,
+    const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src, const VT *__restrict__ valsT,
+    const typename Store<VT>::X *__restrict__ x, const typename Store<VT>::X *__restrict__ g,
+    typename Store<VT>::X *__restrict__ gx, typename Store<VT>::A *__restrict__ gv, int64_t nnz) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    __shared__ A part[kLongWaves];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const bool a_item = int32_t(blockIdx.x) < na;
+    const int32_t r = a_item ? rows[blockIdx.x] : t_rows[blockIdx.x - na];
+    const int32_t *rp = a_item ? row_ptr : t_row_ptr;
+    int64_t a, b;
+    long_slice<Store<VT>::V>(rp[r], rp[r + 1], wave, a, b);
+    A sum = 0;
+    if (a_item && !fused) {
+        if (a < b) range_grad_vals<VT>(a, b, A(g[r]), cols, x, gv, nnz, lane);
+        return;  // uniform over the workgroup
+    }
+    if (a < b) {
+        if (a_item)
+            sum = range_adjoint<VT, IND>(a, b, A(g[r]), cols, t_src, valsT, x, g, gv, nnz, lane);
+        else
+            sum = range_dot<VT, IND>(a, b, t_col, t_src, valsT, g, nnz, lane);
+    }
+    if (lane == 0) part[wave] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        A t = 0;
+        for (int w = 0; w < kLongWaves; ++w) t += part[w];
+        gx[r] = X(t);
+    }
 }
 
 // ------------------------------------------------------------------ plain CSR baseline
@@ -1036,7 +1305,7 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
             const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
             if (nrhs == 1)
                 sr_forward<VT, L, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz,
-                                         reinterpret_cast<A *>(lds), lane);
+                                         reinterpret_cast<A *>(lds), lane, false);
             else
                 sr_forward_mrhs<VT, L, VX, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
                                                   lane);
@@ -1070,7 +1339,7 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
             const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
             if (nrhs == 1)
                 sr_adjoint<VT, L, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x, g, gx,
-                                       gv, d.nnz, d.sym != 0, lds, lane);
+                                       gv, d.nnz, d.sym != 0, lds, lane, false);
             else
                 sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x,
                                                 g, gx, gv, d.nnz, nrhs, lds, lane);
@@ -1163,7 +1432,11 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
                 constexpr int L = decltype(lc)::value;
                 hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(a.nssr), dim3(block), size_t(s.waves) * kStageBytes, st,
                                    a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx, static_cast<const VT *>(vals),
-                                   static_cast<const X *>(x), static_cast<X *>(y), a.nnz);
+                                   static_cast<const X *>(x), static_cast<X *>(y), a.nnz, 1);
+                if (a.nlong > 0)
+                    hipLaunchKernelGGL((k_long_forward<VT>), dim3(a.nlong), dim3(kLongWaves * kWave), 0, st,
+                                       a.long_rows, a.row_ptr, a.col_idx, static_cast<const VT *>(vals),
+                                       static_cast<const X *>(x), static_cast<X *>(y), a.nnz);
                 return hipGetLastError();
             });
         }
@@ -1228,7 +1501,19 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                                        size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
                                        a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
                                        static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       int(a.sym));
+                                       int(a.sym), 1);
+                    // The rows the main kernel left out: long rows of A' for
+                    // grad_vals (and grad_x when fused), long rows of A'^T for
+                    // grad_x otherwise.
+                    const bool fused = a.sym && gx && gv;
+                    const int32_t na = (fused || gv) ? a.nlong : 0;
+                    const int32_t nt = (!fused && gx) ? a.t_nlong : 0;
+                    if (na + nt > 0)
+                        hipLaunchKernelGGL((k_long_adjoint<VT, IND>), dim3(na + nt), dim3(kLongWaves * kWave), 0, st,
+                                           a.long_rows, na, a.t_long_rows, int(fused), a.row_ptr, a.col_idx,
+                                           a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                           static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv),
+                                           a.nnz);
                     return hipGetLastError();
                 });
             }

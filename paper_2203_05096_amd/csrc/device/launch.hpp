@@ -11,6 +11,12 @@
 namespace csrk {
 namespace dev {
 
+// Rows with more nonzeros than this are computed by a workgroup of their own
+// (split over kLongWaves wavefronts) instead of by their super-row's
+// wavefront; the handle lists them at upload.
+constexpr int32_t kLongRow = 1024;
+constexpr int kLongWaves = 16;
+
 // Device arrays of one CSR-k matrix.
 struct Arrays {
     int32_t n = 0;
@@ -30,6 +36,12 @@ struct Arrays {
     const int32_t *t_src = nullptr;
     const void *vals_t = nullptr;  // the handle's values in A'^T order (aligned with t_col)
     bool sym = false;              // pattern of A' is symmetric: A'^T has the pattern of A'
+    // Rows of A' (long_rows) and of A'^T (t_long_rows) longer than kLongRow,
+    // ascending; for a symmetric pattern the two lists are the same.
+    const int32_t *long_rows = nullptr;
+    int32_t nlong = 0;
+    const int32_t *t_long_rows = nullptr;
+    int32_t t_nlong = 0;
 };
 
 // Per-matrix record of a batched launch (device-resident table).

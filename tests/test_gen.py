@@ -61,3 +61,24 @@ def test_c5_small_batch():
     for A, X, s in zip(w["As"], w["xs"], w["sides"]):
         assert A.n == s ** 3 and X.shape == (A.n, 8)
         assert np.array_equal(X.astype(np.float32).astype(np.float64), X)
+
+
+def test_rmat_pattern_properties():
+    from gen.irregular import rmat_matrix
+    A = rmat_matrix(12, 4.0, 5, symmetric=True)
+    B = rmat_matrix(12, 4.0, 5, symmetric=True)
+    assert np.array_equal(A.row_ptr, B.row_ptr) and np.array_equal(A.vals, B.vals)
+    n, rp, ci = A.n, A.row_ptr.astype(np.int64), A.col_idx.astype(np.int64)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    key = rows * n + ci
+    assert np.all(np.diff(key) > 0)  # sorted within rows, no duplicates
+    assert set((ci * n + rows).tolist()) == set(key.tolist())  # symmetric pattern
+    assert np.all(np.isin(np.arange(n) * (n + 1), key))  # every diagonal stored
+    lengths = np.diff(rp)
+    assert lengths.var() > 10 and lengths.max() > 20 * lengths.mean()  # the irregular class (variance above 10)
+    diag = ci == rows
+    off = np.bincount(rows, weights=np.where(diag, 0.0, np.abs(A.vals)), minlength=n)
+    assert np.allclose(A.vals[diag], np.where(off > 0, 1.1 * off, 1.0))
+    N = rmat_matrix(12, 4.0, 6, symmetric=False)
+    rn = np.repeat(np.arange(N.n), np.diff(N.row_ptr))
+    assert set((N.col_idx.astype(np.int64) * N.n + rn).tolist()) != set((rn * N.n + N.col_idx).tolist())

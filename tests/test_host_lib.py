@@ -195,6 +195,18 @@ def test_from_groups_errors():
         assert e.value.name == "CSRK_ERR_ARG"
 
 
+def test_info_counts_long_rows():
+    from gen.irregular import rmat_matrix
+    A = rmat_matrix(14, 8.0, 3, symmetric=True)
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, None)
+    try:
+        info = C.csrk_get_info(h)
+        expect = int((np.diff(A.row_ptr) > 1024).sum())
+        assert expect > 0 and info["long_rows"] == expect and info["max_row"] == int(np.diff(A.row_ptr).max())
+    finally:
+        C.csrk_destroy(h)
+
+
 def test_validation_statuses():
     rp, ci = _path(6)
     rp = np.asarray(rp)
@@ -287,10 +299,14 @@ def test_upload_without_gpu_reports_device_error():
 
 def test_mi355x_model_shape():
     import math
+    from paper_2203_05096_amd import autotune as T
+    assert [T.snap_srs(v) for v in (-5, 1, 2, 3, 5, 7, 10, 14, 28, 40, 52, 57, 61, 71, 80, 81)] == \
+        [1, 1, 2, 3, 4, 6, 8, 12, 24, 32, 48, 64, 64, 64, 64, 96]
+    assert T.snap_srs(5, floor=7) == 8 and T.snap_srs(3, floor=3) == 3 and T.snap_srs(-40, floor=10) == 12
     for r in (1.0, 2.2, 4.9375, 6.953125, 8.19, 13.7, 26.46, 80.0, 300.0, 1000.0):
         n = 10 ** 6
         p = C.csrk_tune(n, int(round(r * n)), "mi355x")
-        srs = max(math.floor(124.21 - 32.80 * math.log(r) + 0.5), math.ceil(256.0 / r))
+        srs = T.snap_srs(math.floor(124.21 - 32.80 * math.log(r) + 0.5), math.ceil(256.0 / r))
         assert (p["srs"], p["ssrs"], p["waves_per_wg"]) == (srs, 2, 2), r
         assert p["lanes_per_row"] == (1 if r <= 6 else 2 if r <= 24 else 4 if r <= 48 else 8 if r <= 96 else 16)
         assert p["reorder"] == 0 and p["k"] == 3
