@@ -8,13 +8,14 @@ size choice and upload run before the timed region, as the paper times only
 the kernels on data already on the GPU.  Prints one JSON line (the last line
 of stdout).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5] [--store f64|f32|bf16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c5|irr] [--store f64|f32|bf16]
                     [--no-cpu] [--no-extras] [--copy-calibration]
 
 Other workloads: c3 = 3D 27-point 100^3 (precision study), c4 = 2D 9-point
 2048^2 with 10% of off-diagonals dropped (nonsymmetric, FP32), c5 = 64 3D
 7-point Laplacians of uneven size with 8 right-hand sides each, in one
-persistent batched launch per direction (FP32).
+persistent batched launch per direction (FP32), irr = an R-MAT graph of 2^20
+rows (power-law row lengths, the paper's irregular class; FP64).
 """
 
 from __future__ import annotations
@@ -209,7 +210,7 @@ class Batch:
         self.C, self.store, self.nrhs = C, store, nrhs
 
         def one(A):
-            p = C.csrk_tune(A.n, A.nnz, "mi355x")
+            p = C.csrk_tune_rhs(A.n, A.nnz, nrhs, "mi355x")
             return CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store)
         t = time.perf_counter()
         with cf.ThreadPoolExecutor(16) as ex:
@@ -254,8 +255,9 @@ class Batch:
 
 
 WORKLOAD_NAMES = {"c2": "3d7pt_128cube_scrambled_forward_adjoint", "c3": "3d27pt_100cube_forward_adjoint",
-                  "c4": "2d9pt_2048sq_drop10_forward_adjoint", "c5": "batch64_3d7pt_sides16to96_8rhs_forward_adjoint"}
-DEFAULT_STORE = {"c2": "f64", "c3": "f64", "c4": "f32", "c5": "f32"}
+                  "c4": "2d9pt_2048sq_drop10_forward_adjoint", "c5": "batch64_3d7pt_sides16to96_8rhs_forward_adjoint",
+                  "irr": "rmat_2pow20_rows_sym_forward_adjoint"}
+DEFAULT_STORE = {"c2": "f64", "c3": "f64", "c4": "f32", "c5": "f32", "irr": "f64"}
 
 
 def main():

@@ -27,3 +27,6 @@ from .stencils import (  # noqa: F401
     tuning_suite,
     WORKLOADS,
 )
+from .irregular import rmat_matrix, rmat_pattern, workload_irregular  # noqa: E402,F401
+
+WORKLOADS = dict(WORKLOADS, irr=workload_irregular)

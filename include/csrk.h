@@ -51,6 +51,10 @@ typedef enum csrk_status {
 
 /* Storage type of the matrix values.  F64 pairs with FP64 vectors and FP64
  * accumulation; F32 and BF16 pair with FP32 vectors and FP32 accumulation. */
+/* Rows with more nonzeros than this are computed by a workgroup of their own
+ * instead of by their super-row's wavefront (see csrk_info.long_rows). */
+#define CSRK_LONG_ROW 1024
+
 typedef enum csrk_dtype { CSRK_F64 = 0, CSRK_F32 = 1, CSRK_BF16 = 2 } csrk_dtype;
 
 /* Size models.  VOLTA and AMPERE are the paper's fitted formulas (Section 4.1);
@@ -90,9 +94,9 @@ typedef struct csrk_info {
     int32_t max_ssr_rows;     /* largest row count of a super-super-row */
     int32_t on_device;        /* 1 when device arrays exist */
     int32_t store;            /* csrk_dtype of the device values (valid when on_device) */
-    int32_t long_rows;        /* rows with more than 1024 nonzeros: each is computed by a
-                                 workgroup of its own (Section 5.5 names splitting dense
-                                 rows as the fix for irregular matrices) */
+    int32_t long_rows;        /* rows with more than CSRK_LONG_ROW nonzeros: each is computed
+                                 by a workgroup of its own (Section 5.5 names computing
+                                 dense rows in parallel as the fix for irregular matrices) */
     csrk_params params;
 } csrk_info;
 
@@ -116,6 +120,18 @@ const char *csrk_last_error_detail(void);
 csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out);
 
 /*
+ * csrk_tune_rhs — csrk_tune for a matrix that will be multiplied by blocks
+ * of nrhs right-hand sides (nrhs >= 1; nrhs == 1 is csrk_tune).  The paper's
+ * model is for one vector (Section 4.1); for nrhs > 1 the MI355X model keeps
+ * its SRS and sets SSRS = waves per workgroup = 8, this library's measurement
+ * on the multi-right-hand-side kernels (a batch of 64 7-point matrices with
+ * 8 right-hand sides: forward + adjoint 1.84 ms at SSRS 8 against 2.46 ms at
+ * the single-vector choice of 2).  VOLTA/AMPERE ignore nrhs.
+ * Errors: as csrk_tune, and CSRK_ERR_ARG for nrhs < 1.
+ */
+csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out);
+
+/*
  * csrk_build_host — validate the CSR input, build the symmetrised graph,
  * reorder (Band-k / RCM / none), apply the symmetric permutation (columns
  * sorted within rows) and form sr_ptr / ssr_ptr (Section 2.2).  Host only: no
@@ -124,6 +140,14 @@ csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out
  * Columns may be unsorted within a row; duplicates are rejected.  p == NULL
  * uses csrk_tune(n, nnz, CSRK_MODEL_MI355X).  The result is deterministic:
  * the same input gives a bit-identical structure.
+ * Irregular matrices: after the grouping, a super-row whose nonzeros (rows
+ * longer than CSRK_LONG_ROW not counted) exceed the budget
+ * B = max(2048, ceil(4 * SRS * nnz / n)) is cut greedily into consecutive
+ * pieces of at most B, each piece becoming a super-row; the pieces of a
+ * super-super-row are regrouped SSRS at a time.  A regular matrix (no
+ * super-row above B) keeps the plain grouping.  This is this library's
+ * extension: the paper leaves load balance on irregular matrices as future
+ * work (Section 5.5).
  * Errors: CSRK_ERR_ARG, CSRK_ERR_BAD_ROWPTR, CSRK_ERR_COL_RANGE,
  * CSRK_ERR_DUPLICATE, CSRK_ERR_ALLOC.
  */

@@ -63,6 +63,8 @@ _SIGS = {
     "csrk_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "csrk_last_error_detail": ([], ctypes.c_char_p),
     "csrk_tune": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(csrk_params)], ctypes.c_int),
+    "csrk_tune_rhs": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(csrk_params)],
+                      ctypes.c_int),
     "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params),
                          ctypes.POINTER(_h)], ctypes.c_int),
     "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, _i32p, ctypes.c_int32, _i32p,
@@ -159,6 +161,13 @@ def csrk_tune(n: int, nnz: int, model: str = "mi355x") -> dict:
     p = csrk_params()
     _check(lib().csrk_tune(int(n), int(nnz), MODELS[model] if isinstance(model, str) else int(model), ctypes.byref(p)),
            "csrk_tune")
+    return p.as_dict()
+
+
+def csrk_tune_rhs(n: int, nnz: int, nrhs: int, model: str = "mi355x") -> dict:
+    p = csrk_params()
+    _check(lib().csrk_tune_rhs(int(n), int(nnz), int(nrhs), MODELS[model] if isinstance(model, str) else int(model),
+                               ctypes.byref(p)), "csrk_tune_rhs")
     return p.as_dict()
 
 

@@ -38,6 +38,7 @@ struct csrk_matrix {
     // rows of A' / A'^T longer than csrk::dev::kLongRow (t_ only if nonsymmetric)
     std::vector<int32_t> long_rows, t_long_rows;
     int32_t *d_long = nullptr, *d_t_long = nullptr;
+    csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
 };
 
 struct csrk_batch_s {
@@ -184,7 +185,42 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.nlong = static_cast<int32_t>(h->long_rows.size());
     a.t_long_rows = sym ? h->d_long : h->d_t_long;
     a.t_nlong = static_cast<int32_t>(sym ? h->long_rows.size() : h->t_long_rows.size());
+    a.split_fwd = h->split_fwd;
+    a.split_adj = h->split_adj;
     return a;
+}
+
+// Work-balanced XCD ranges over the super-super-rows: the cost of a row is
+// its nonzeros (0 for rows longer than kLongRow, which run elsewhere) plus 1,
+// summed over row_ptr and, when given, a second row pointer array (the
+// adjoint's transposed rows).  Range x ends at the first SSR whose prefix cost
+// reaches x/8 of the total.
+csrk::dev::XcdSplit xcd_split(const csrk_matrix *h, const std::vector<int32_t> &rp,
+                              const std::vector<int32_t> *rp2) {
+    using csrk::dev::kXcds;
+    const int64_t nssr = int64_t(h->ssr_ptr.size()) - 1;
+    std::vector<int64_t> prefix(size_t(nssr) + 1, 0);
+    auto row_cost = [](const std::vector<int32_t> &p, int32_t i) -> int64_t {
+        const int64_t len = int64_t(p[i + 1]) - p[i];
+        return len > csrk::dev::kLongRow ? 0 : len;
+    };
+    for (int64_t t = 0; t < nssr; ++t) {
+        int64_t c = 0;
+        for (int32_t i = h->sr_ptr[h->ssr_ptr[t]]; i < h->sr_ptr[h->ssr_ptr[t + 1]]; ++i)
+            c += 1 + row_cost(rp, i) + (rp2 ? row_cost(*rp2, i) : 0);
+        prefix[t + 1] = prefix[t] + c;
+    }
+    csrk::dev::XcdSplit sp;
+    const int64_t total = prefix[nssr];
+    sp.b[0] = 0;
+    for (int x = 1; x < kXcds; ++x) {
+        const int64_t target = (total * x + kXcds - 1) / kXcds;
+        const int64_t t = std::lower_bound(prefix.begin(), prefix.end(), target) - prefix.begin();
+        sp.b[x] = static_cast<int32_t>(std::max<int64_t>(sp.b[x - 1], std::min<int64_t>(t, nssr)));
+    }
+    sp.b[kXcds] = static_cast<int32_t>(nssr);
+    for (int x = 0; x < kXcds; ++x) sp.width = std::max(sp.width, sp.b[x + 1] - sp.b[x]);
+    return sp;
 }
 
 // Rows whose length (from a row pointer array) exceeds kLongRow, ascending.
@@ -259,6 +295,19 @@ csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out
     });
 }
 
+csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out) {
+    return guard([&] {
+        if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
+        csrk_status s = csrk::tune(n, nnz, model, out);
+        if (s != CSRK_OK) {
+            set_detail("csrk_tune_rhs needs n > 0, nnz > 0, a known model and an output pointer");
+            return s;
+        }
+        if (model == CSRK_MODEL_MI355X && nrhs > 1) out->ssrs = out->waves_per_wg = 8;
+        return CSRK_OK;
+    });
+}
+
 csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                             const double *vals, const csrk_params *p, csrk_handle *out) {
     return guard([&] {
@@ -276,6 +325,7 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
             std::iota(id.begin(), id.end(), 0);
             gr = csrk::chunked(std::move(id), q.srs, q.ssrs);
         }
+        csrk::balance(gr, row_ptr, csrk::sr_budget(n, nnz, q.srs), q.ssrs);
         auto h = new csrk_matrix();
         try {
             h->n = n;
@@ -342,6 +392,8 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
             h->t_long_rows = h->trans.symmetric ? std::vector<int32_t>() : long_rows_of(h->trans.t_row_ptr);
             if (!h->long_rows.empty()) h->d_long = upload_array(h->long_rows, "long rows");
             if (!h->t_long_rows.empty()) h->d_t_long = upload_array(h->t_long_rows, "transposed long rows");
+            h->split_fwd = xcd_split(h, h->row_ptr, nullptr);
+            h->split_adj = h->trans.symmetric ? h->split_fwd : xcd_split(h, h->row_ptr, &h->trans.t_row_ptr);
             hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
             hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
             h->on_device = true;

@@ -16,7 +16,10 @@
 // Workgroups are renumbered so that each of the 8 XCDs (which receive
 // workgroups round-robin and each own an L2) works on a contiguous range of
 // SSRs; neighbouring SSRs share most of their x window after a band-limiting
-// ordering, so x is fetched into each L2 roughly once.
+// ordering, so x is fetched into each L2 roughly once.  The ranges are cut by
+// work (nonzeros plus rows), not by SSR count: on a power-law matrix the
+// band ordering gathers the heavy rows together, and equal counts left one
+// XCD with nearly half of the work.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -33,7 +36,6 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kStageEntries = 512;                 // nonzeros staged per window and wavefront
 constexpr int kStageBytes = kStageEntries * 8;     // LDS for one window of products (FP64 worst case)
-constexpr int kXcds = 8;
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(uint32_t(b) << 16); }
 
@@ -60,6 +62,14 @@ struct Store<uint16_t> {
     static constexpr int V = 8;
     __device__ static float widen(uint16_t v) { return bf16_to_f32(v); }
 };
+
+// Super-super-row of this workgroup under the work-balanced XCD ranges, or -1
+// for a padding block.
+__device__ __forceinline__ int32_t ssr_of_block(const XcdSplit &sp) {
+    const int32_t xcd = int32_t(blockIdx.x) % kXcds;
+    const int32_t t = sp.b[xcd] + int32_t(blockIdx.x) / kXcds;
+    return t < sp.b[xcd + 1] ? t : -1;
+}
 
 // Logical block index such that each XCD (blockIdx % 8 under round-robin
 // dispatch) receives a contiguous range of logical indices.  A bijection on
@@ -421,7 +431,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
                                                     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                                     typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                                    int skip_long) {
+                                                    int skip_long, XcdSplit split) {
     using A = typename Store<VT>::A;
     constexpr int CAP = kStageEntries;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -429,7 +439,8 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     A *buf = reinterpret_cast<A *>(smem) + wave * CAP;
-    const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int32_t t = ssr_of_block(split);
+    if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_forward<VT, L, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y, nnz,
@@ -617,13 +628,14 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
                                                          const int32_t *__restrict__ cols, const VT *__restrict__ vals,
                                                          const typename Store<VT>::X *__restrict__ x,
                                                          typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                                         int nrhs) {
+                                                         int nrhs, XcdSplit split) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     unsigned char *lds = smem + size_t(wave) * kMrhsLds;
-    const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int32_t t = ssr_of_block(split);
+    if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_forward_mrhs<VT, RL, VX, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals,
@@ -1076,13 +1088,14 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
                                                        const typename Store<VT>::X *__restrict__ g,
                                                        typename Store<VT>::X *__restrict__ gx,
                                                        typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym,
-                                                       int skip_long) {
+                                                       int skip_long, XcdSplit split) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     unsigned char *lds = smem + size_t(wave) * kAdjointLds;
-    const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int32_t t = ssr_of_block(split);
+    if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
@@ -1095,13 +1108,14 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr, const int32_t *__restrict__ t_col,
     const int32_t *__restrict__ t_src, const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
     const typename Store<VT>::X *__restrict__ g, typename Store<VT>::X *__restrict__ gx,
-    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs) {
+    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, XcdSplit split) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     unsigned char *lds = smem + size_t(wave) * kMrhsLds;
-    const int32_t t = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int32_t t = ssr_of_block(split);
+    if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
@@ -1430,9 +1444,10 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
         if (nrhs == 1) {
             return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
                 constexpr int L = decltype(lc)::value;
-                hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(a.nssr), dim3(block), size_t(s.waves) * kStageBytes, st,
-                                   a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx, static_cast<const VT *>(vals),
-                                   static_cast<const X *>(x), static_cast<X *>(y), a.nnz, 1);
+                hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(a.split_fwd.width * kXcds), dim3(block),
+                                   size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                   static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
+                                   a.nnz, 1, a.split_fwd);
                 if (a.nlong > 0)
                     hipLaunchKernelGGL((k_long_forward<VT>), dim3(a.nlong), dim3(kLongWaves * kWave), 0, st,
                                        a.long_rows, a.row_ptr, a.col_idx, static_cast<const VT *>(vals),
@@ -1445,10 +1460,10 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
             constexpr int VX = decltype(vc)::value;
             return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                 constexpr int RL = decltype(rc)::value;
-                hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, RL, VX>), dim3(a.nssr), dim3(block),
+                hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, RL, VX>), dim3(a.split_fwd.width * kXcds), dim3(block),
                                    size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
                                    static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
-                                   a.nnz, nrhs);
+                                   a.nnz, nrhs, a.split_fwd);
                 return hipGetLastError();
             });
         });
@@ -1497,11 +1512,11 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
             if (nrhs == 1) {
                 return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
                     constexpr int LL = decltype(lc)::value;
-                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(a.nssr), dim3(block),
+                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(a.split_adj.width * kXcds), dim3(block),
                                        size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
                                        a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
                                        static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       int(a.sym), 1);
+                                       int(a.sym), 1, a.split_adj);
                     // The rows the main kernel left out: long rows of A' for
                     // grad_vals (and grad_x when fused), long rows of A'^T for
                     // grad_x otherwise.
@@ -1522,11 +1537,11 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                 constexpr int VX = decltype(vc)::value;
                 return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                     constexpr int RL = decltype(rc)::value;
-                    hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.nssr), dim3(block),
-                                       size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
-                                       a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                    hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.split_adj.width * kXcds),
+                                       dim3(block), size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                       a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
                                        static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       nrhs);
+                                       nrhs, a.split_adj);
                     return hipGetLastError();
                 });
             });

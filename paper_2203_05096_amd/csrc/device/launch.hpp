@@ -14,8 +14,18 @@ namespace dev {
 // Rows with more nonzeros than this are computed by a workgroup of their own
 // (split over kLongWaves wavefronts) instead of by their super-row's
 // wavefront; the handle lists them at upload.
-constexpr int32_t kLongRow = 1024;
+constexpr int32_t kLongRow = CSRK_LONG_ROW;
 constexpr int kLongWaves = 16;
+
+// Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
+// by block index.  Block b runs super-super-row b[b % 8] + b / 8 of XCD b % 8's
+// contiguous range [b[x], b[x+1]); blocks past the end of their range exit at
+// once.  The ranges are cut so that each XCD gets about the same work.
+constexpr int kXcds = 8;
+struct XcdSplit {
+    int32_t b[kXcds + 1] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t width = 0;  // largest range: the grid is width * kXcds blocks
+};
 
 // Device arrays of one CSR-k matrix.
 struct Arrays {
@@ -42,6 +52,8 @@ struct Arrays {
     int32_t nlong = 0;
     const int32_t *t_long_rows = nullptr;
     int32_t t_nlong = 0;
+    XcdSplit split_fwd;  // by the forward's work (rows of A')
+    XcdSplit split_adj;  // by the adjoint's work (rows of A' and of A'^T)
 };
 
 // Per-matrix record of a batched launch (device-resident table).

@@ -299,4 +299,53 @@ Grouping from_sizes(std::vector<int32_t> perm, const int32_t *sr_sizes, int32_t 
     return r;
 }
 
+int64_t sr_budget(int32_t n, int64_t nnz, int32_t srs) {
+    if (n <= 0) return 2048;
+    const int64_t q = (4 * int64_t(srs) * nnz + n - 1) / n;
+    return std::max<int64_t>(2048, q);
+}
+
+void balance(Grouping &g, const int32_t *row_ptr, int64_t budget, int32_t ssrs) {
+    const int64_t nsr = int64_t(g.sr_ptr.size()) - 1;
+    if (nsr <= 0) return;
+    auto cost = [&](int32_t i) -> int64_t {
+        const int32_t r = g.perm[i];
+        const int64_t len = int64_t(row_ptr[r + 1]) - row_ptr[r];
+        return len > CSRK_LONG_ROW ? 0 : len;
+    };
+    std::vector<int64_t> sr_sizes, ssr_sizes;
+    sr_sizes.reserve(size_t(nsr));
+    bool split_any = false;
+    for (size_t t = 0; t + 1 < g.ssr_ptr.size(); ++t) {
+        const size_t first = sr_sizes.size();
+        for (int32_t s = g.ssr_ptr[t]; s < g.ssr_ptr[t + 1]; ++s) {
+            const int32_t a = g.sr_ptr[s], b = g.sr_ptr[s + 1];
+            int64_t total = 0;
+            for (int32_t i = a; i < b; ++i) total += cost(i);
+            if (total <= budget) {
+                sr_sizes.push_back(b - a);
+                continue;
+            }
+            split_any = true;
+            int32_t start = a;
+            int64_t acc = 0;
+            for (int32_t i = a; i < b; ++i) {
+                const int64_t c = cost(i);
+                if (i > start && acc + c > budget) {
+                    sr_sizes.push_back(i - start);
+                    start = i;
+                    acc = 0;
+                }
+                acc += c;
+            }
+            sr_sizes.push_back(b - start);
+        }
+        const int32_t pieces = static_cast<int32_t>(sr_sizes.size() - first);
+        for (int32_t q = 0; q < pieces; q += ssrs) ssr_sizes.push_back(std::min<int64_t>(ssrs, pieces - q));
+    }
+    if (!split_any) return;
+    g.sr_ptr = running(sr_sizes);
+    g.ssr_ptr = running(ssr_sizes);
+}
+
 }  // namespace csrk

@@ -86,6 +86,15 @@ Grouping rcm_chunked(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, 
 Grouping from_sizes(std::vector<int32_t> perm, const int32_t *sr_sizes, int32_t nsr, const int32_t *ssr_sizes,
                     int32_t nssr);
 
+// Nonzero budget of a super-row: max(2048, ceil(4 * srs * nnz / n)).
+int64_t sr_budget(int32_t n, int64_t nnz, int32_t srs);
+
+// Cuts every super-row whose cost (its rows' nonzeros, rows longer than
+// CSRK_LONG_ROW counted as 0) exceeds `budget` greedily into consecutive
+// pieces of cost <= budget, and regroups the pieces of each super-super-row
+// `ssrs` at a time.  row_ptr is the input matrix's (rows in input order).
+void balance(Grouping &g, const int32_t *row_ptr, int64_t budget, int32_t ssrs);
+
 // ---------------------------------------------------------------- CSR
 
 // Checks row_ptr / col_idx; throws Error with the matching status.

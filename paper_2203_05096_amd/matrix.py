@@ -59,11 +59,13 @@ class CsrkMatrix:
         self.val_dtype = _VAL_DTYPE[store]
 
     @classmethod
-    def from_csr(cls, row_ptr, col_idx, vals, store: str = "f64", model: str = "mi355x", params=None):
+    def from_csr(cls, row_ptr, col_idx, vals, store: str = "f64", model: str = "mi355x", params=None,
+                 nrhs: int = 1):
+        """``nrhs``: width of the right-hand-side blocks the matrix will mostly be used with (tuning only)."""
         if not torch.cuda.is_available():
             raise RuntimeError("CsrkMatrix needs a GPU")
         if params is None:
-            params = C.csrk_tune(len(row_ptr) - 1, int(np.asarray(row_ptr)[-1]), model)
+            params = C.csrk_tune_rhs(len(row_ptr) - 1, int(np.asarray(row_ptr)[-1]), nrhs, model)
         h = C.csrk_build(row_ptr, col_idx, vals, params, store)
         return cls(h, store)
 

@@ -17,9 +17,9 @@ from paper_2203_05096_amd import _capi as C  # noqa: E402
 from paper_2203_05096_amd.matrix import CsrkBatch, CsrkMatrix  # noqa: E402
 
 
-def _build_all(mats, store="f32"):
+def _build_all(mats, store="f32", nrhs=8):
     def one(A):
-        p = C.csrk_tune(A.n, A.nnz, "mi355x")
+        p = C.csrk_tune_rhs(A.n, A.nnz, nrhs, "mi355x")
         return CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store)
     with cf.ThreadPoolExecutor(8) as ex:
         return list(ex.map(one, mats))

@@ -100,12 +100,7 @@ def _lib_structure(row_ptr, col_idx, vals, srs, ssrs, reorder="bandk"):
 
 def _assert_same_as_oracle(A_rp, A_ci, A_vals, srs, ssrs, reorder="bandk"):
     s, info = _lib_structure(A_rp, A_ci, A_vals, srs, ssrs, reorder)
-    if reorder == "bandk":
-        perm, sr_ptr, ssr_ptr = OB.bandk_v1(A_rp, A_ci, srs, ssrs)
-    elif reorder == "rcm":
-        perm, sr_ptr, ssr_ptr = OB.reorder_rcm(A_rp, A_ci, srs, ssrs)
-    else:
-        perm, sr_ptr, ssr_ptr = OB.reorder_none(len(A_rp) - 1, srs, ssrs)
+    perm, sr_ptr, ssr_ptr = OB.build_grouping(A_rp, A_ci, srs, ssrs, reorder)
     rp2, ci2, v2, vmap = OB.apply_permutation(A_rp, A_ci, A_vals, perm)
     assert np.array_equal(s["perm"], perm)
     assert np.array_equal(s["sr_ptr"], sr_ptr)
@@ -193,6 +188,16 @@ def test_from_groups_errors():
         with pytest.raises(C.CsrkError) as e:
             C.csrk_build_from_groups(rp, ci, None, perm, srz, ssrz, _params(1, 1))
         assert e.value.name == "CSRK_ERR_ARG"
+
+
+@pytest.mark.parametrize("reorder", ["bandk", "rcm", "none"])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_bitexact_irregular_budget_split(reorder, symmetric):
+    """R-MAT rows (power-law lengths): heavy super-rows are cut by the nonzero budget, identically to the oracle."""
+    from gen.irregular import rmat_matrix
+    A = rmat_matrix(13, 6.0, 17, symmetric=symmetric)
+    s, info = _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 64, 4, reorder)
+    assert info["nsr"] > -(-A.n // 64)  # at least one super-row was split
 
 
 def test_info_counts_long_rows():
@@ -327,6 +332,19 @@ def test_autotune_fit_and_evaluate():
     ev = T.evaluate(res, f)
     assert all(e["ratio"] >= 1.0 for e in ev) and ev[0]["model_srs"] in (48, 64)
     assert all(e["model_ssrs"] in (2, 4) for e in ev)
+
+
+def test_tune_rhs():
+    for n, nnz in ((4096, 20224), (10 ** 6, 26463592), (2097152, 14581760)):
+        one = C.csrk_tune(n, nnz, "mi355x")
+        assert C.csrk_tune_rhs(n, nnz, 1, "mi355x") == one
+        many = C.csrk_tune_rhs(n, nnz, 8, "mi355x")
+        assert (many["srs"], many["lanes_per_row"]) == (one["srs"], one["lanes_per_row"])
+        assert many["ssrs"] == many["waves_per_wg"] == 8
+        assert C.csrk_tune_rhs(n, nnz, 8, "ampere") == C.csrk_tune(n, nnz, "ampere")
+    with pytest.raises(C.CsrkError) as e:
+        C.csrk_tune_rhs(100, 500, 0, "mi355x")
+    assert e.value.name == "CSRK_ERR_ARG"
 
 
 def test_autotune_helpers_match_library_model():
