@@ -197,6 +197,37 @@ class Single:
                                       self.stream):
             raise RuntimeError(self.C.csrk_last_error_detail())
 
+    def accuracy(self, torch, x):
+        """Forward error of y against an FP64 product computed with scipy.sparse on the input order (values
+        rounded to the storage type first, so the figure is the kernel's rounding only), relative to
+        sum_j |a_ij||x_j| per row; also against the FP64 values (storage rounding included)."""
+        import scipy.sparse as sp
+        A = self.A
+        self.fwd()
+        torch.cuda.synchronize()
+        perm = self.M.structure()["perm"]
+        y = np.empty(A.n)
+        y[perm] = self.y.double().cpu().numpy()
+        vals = A.vals
+        if self.store != "f64":
+            v32 = A.vals.astype(np.float32)
+            if self.store == "bf16":
+                u = v32.view(np.uint32).astype(np.uint64)
+                u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16  # round to nearest even (finite values)
+                v32 = u.astype(np.uint32).view(np.float32)
+            vals = v32.astype(np.float64)
+        xr = x if self.store == "f64" else x.astype(np.float32).astype(np.float64)
+        M = sp.csr_matrix((vals, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+        M64 = sp.csr_matrix((A.vals, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+        scale = abs(M64) @ np.abs(xr)
+        scale[scale == 0] = 1.0
+        e_kernel = np.abs(y - M @ xr) / scale
+        e_total = np.abs(y - M64 @ xr) / scale
+        return {"max_rel_err_vs_stored_values": float(e_kernel.max()), "rms_rel_err_vs_stored_values":
+                float(np.sqrt(np.mean(e_kernel ** 2))), "max_rel_err_vs_fp64_values": float(e_total.max()),
+                "rms_rel_err_vs_fp64_values": float(np.sqrt(np.mean(e_total ** 2))),
+                "reference": "scipy.sparse FP64 product, error / sum_j |a_ij||x_j| per row"}
+
     def config(self):
         return {"n": self.A.n, "nnz": self.A.nnz, "csrk_params": self.params, "nsr": self.nsr, "nssr": self.nssr,
                 "bandwidth_after_reorder": self.info["bandwidth"], "build_seconds": round(self.build_s, 2)}
@@ -354,6 +385,9 @@ def main():
                 if Mp is not W.M:
                     Mp.close()
             extras["plain_csr"] = plain
+    if isinstance(W, Single):
+        extras["accuracy"] = W.accuracy(torch, w["x"])
+        log(f"accuracy {extras['accuracy']}")
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         b = torch.empty_like(a)
