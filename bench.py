@@ -157,6 +157,37 @@ def cpu_baseline(mats, xs, gs, budget_s=12.0):
             "cpu": cpu_model()}
 
 
+def cpu_csrk(C, A, x, W, reps=20):
+    """The library's host CPU kernel (csrk_spmv_host, OpenMP over super-super-rows) on this matrix: the
+    Band-k structure of the GPU handle, and plain CSR (one row per super-row, one super-row per
+    super-super-row) in input order and in Band-k order.  FP64, all host threads; mean of `reps` runs
+    after 3 warm-ups."""
+    def t(h, xp):
+        y = np.empty_like(xp)
+        for _ in range(3):
+            C.csrk_spmv_host(h, xp, y)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            C.csrk_spmv_host(h, xp, y)
+        return (time.perf_counter() - t0) / reps * 1e6
+    out = {"csrk_bandk_us": round(t(W.M.handle, x[W.M.structure()["perm"]]), 1)}
+    for name, reorder in (("plain_input_order_us", "none"), ("plain_bandk_order_us", "bandk")):
+        if reorder == "none":
+            p = {"k": 3, "srs": 1, "ssrs": 1, "lanes_per_row": 1, "waves_per_wg": 1, "reorder": "none"}
+            h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
+        else:  # Band-k rows, regrouped one row per super-row
+            s = W.M.structure()
+            n = A.n
+            ones = np.ones(n, np.int32)
+            h = C.csrk_build_from_groups(A.row_ptr, A.col_idx, A.vals, s["perm"], ones, ones,
+                                         dict(W.params, srs=1, ssrs=1))
+        out[name] = round(t(h, x[C.csrk_copy_structure(h)["perm"]]), 1)
+        C.csrk_destroy(h)
+    out["threads"] = os.cpu_count()
+    out["note"] = "FP64 forward on the host, csrk_spmv_host with the OpenMP default thread count"
+    return out
+
+
 class Single:
     """One CSR-k matrix (workloads c2, c3, c4)."""
 
@@ -385,6 +416,15 @@ def main():
                 if Mp is not W.M:
                     Mp.close()
             extras["plain_csr"] = plain
+            # CSR-2 (one grouping level) on the same matrix, same sizes
+            q = dict(W.params, k=2)
+            M2 = CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, q, store), store)
+            x2 = torch.from_numpy(x[M2.structure()["perm"]]).to(dtype=W.xd.dtype).cuda()
+            y2 = torch.empty_like(x2)
+            _, (k2,) = timed_launches(torch, [lambda: M2.spmv(x2, y2)], 50, 5)
+            extras["csr2_forward_us"] = round(k2 * 1e3, 2)
+            M2.close()
+            extras["cpu_csrk"] = cpu_csrk(C, A, x, W)
     if isinstance(W, Single):
         extras["accuracy"] = W.accuracy(torch, w["x"])
         log(f"accuracy {extras['accuracy']}")

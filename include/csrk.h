@@ -68,7 +68,10 @@ typedef enum csrk_reorder { CSRK_REORDER_BANDK = 0, CSRK_REORDER_RCM = 1, CSRK_R
 /* Tuning parameters.  srs = rows per super-row (SRS), ssrs = super-rows per
  * super-super-row (SSRS) (Section 4.1).  lanes_per_row (1, 2, 4, ..., 64) is
  * the number of wavefront lanes that reduce one row; waves_per_wg (1..16) the
- * wavefronts per workgroup.  k must be 3. */
+ * wavefronts per workgroup.  k is 3 (CSR-3) or 2 (CSR-2, Section 2.2: one
+ * coarsening level, Band-k orders the coarse graph by reverse Cuthill-McKee;
+ * the super-rows are then grouped ssrs at a time in order for the launch,
+ * which is what ssr_ptr holds for k = 2). */
 typedef struct csrk_params {
     int32_t k;
     int32_t srs;
@@ -227,13 +230,24 @@ csrk_status csrk_spmv_plain(csrk_handle h, const void *vals_dev, const void *x_d
                             void *stream);
 
 /*
+ * csrk_spmv_host — the product on the host CPU over the same handle (the
+ * paper's CPU kernel, Section 2.2 listing): super-super-rows in parallel
+ * (OpenMP, static schedule), then their super-rows, then their rows, each row
+ * summed left to right in FP64.  x (n doubles) and y (n doubles) are host
+ * arrays in permuted space; values are the handle's FP64 master copy.
+ * nthreads <= 0 uses the OpenMP default.  Needs no device.  Errors:
+ * CSRK_ERR_ARG for a null handle or pointer.
+ */
+csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nthreads);
+
+/*
  * csrk_spmv_adjoint — gradients of L = <g', A' x'> (not in the paper):
  * grad_x' = A'^T g' (n x nrhs, same type as x) and grad_vals'[k] =
  * sum_c g'[row(k), c] x'[col(k), c] (nnz values in CSR-k order, FP64 for F64
- * storage, FP32 otherwise).  Either output may be NULL to skip it.  grad_x is
- * accumulated with device atomics, so its summation order (and last bits)
- * may vary between runs; grad_vals is deterministic.  Same errors as
- * csrk_spmv.
+ * storage, FP32 otherwise).  Either output may be NULL to skip it.  No
+ * atomics: grad_x is computed row by row over the transposed index structure
+ * built at upload, so both outputs are the same on every run.  Same errors
+ * as csrk_spmv.
  */
 csrk_status csrk_spmv_adjoint(csrk_handle h, const void *vals_dev, const void *x_dev, const void *g_dev,
                               void *grad_x_dev, void *grad_vals_dev, int32_t nrhs, void *stream);

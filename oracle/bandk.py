@@ -232,6 +232,25 @@ def bandk_v1(row_ptr, col_idx, srs: int, ssrs: int):
     return np.asarray(perm, dtype=np.int64), sr_ptr, ssr_ptr
 
 
+def bandk_k2(row_ptr, col_idx, srs: int, group: int):
+    """Band-k with k = 2 (CSR-2): G1 = Quotient(Aggregate(G0, SRS)); the SRs are the vertices of G1 in
+    RCM(G1) order; perm = Expand(G0, that order).  CSR-2 has no SSR level: for the launch the SRs are grouped
+    ``group`` at a time in order.  Returns ``(perm, sr_ptr, ssr_ptr)``."""
+    if srs < 1 or group < 1:
+        raise ValueError("SRS and the group size must be >= 1")
+    G0 = graph_from_csr(row_ptr, col_idx)
+    if G0.n == 0:
+        return np.zeros(0, np.int64), np.zeros(1, np.int64), np.zeros(1, np.int64)
+    agg1, ch1, id1 = aggregate(G0, srs)
+    G1 = quotient(G0, agg1, id1)
+    order1 = reverse_cuthill_mckee(G1)
+    perm = expand(G0, order1, ch1)
+    nsr = len(order1)
+    sr_ptr = running_counts([len(ch1[s]) for s in order1])
+    ssr_ptr = running_counts([min(group, nsr - t) for t in range(0, nsr, group)])
+    return np.asarray(perm, dtype=np.int64), sr_ptr, ssr_ptr
+
+
 def chunked(perm, srs: int, ssrs: int):
     """SRs of SRS consecutive rows in ``perm`` order, SSRs of SSRS consecutive SRs (last ones may be short)."""
     n = len(perm)
@@ -321,11 +340,11 @@ def balance(perm, sr_ptr, ssr_ptr, row_ptr, srs: int, ssrs: int):
     return running_counts(sr_sizes), running_counts(ssr_sizes)
 
 
-def build_grouping(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk"):
-    """Ordering + grouping as the library's host build forms it: the reordering's grouping (Band-k, RCM
-    with fixed chunks, or the input order with fixed chunks), then step 8."""
+def build_grouping(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk", k: int = 3):
+    """Ordering + grouping as the library's host build forms it: the reordering's grouping (Band-k with k
+    levels, RCM with fixed chunks, or the input order with fixed chunks), then step 8."""
     if reorder == "bandk":
-        perm, sr_ptr, ssr_ptr = bandk_v1(row_ptr, col_idx, srs, ssrs)
+        perm, sr_ptr, ssr_ptr = (bandk_v1 if k == 3 else bandk_k2)(row_ptr, col_idx, srs, ssrs)
     elif reorder == "rcm":
         perm, sr_ptr, ssr_ptr = reorder_rcm(row_ptr, col_idx, srs, ssrs)
     else:

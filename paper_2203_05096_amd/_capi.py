@@ -65,6 +65,7 @@ _SIGS = {
     "csrk_tune": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.POINTER(csrk_params)], ctypes.c_int),
     "csrk_tune_rhs": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(csrk_params)],
                       ctypes.c_int),
+    "csrk_spmv_host": ([_h, _f64p, _f64p, ctypes.c_int32], ctypes.c_int),
     "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params),
                          ctypes.POINTER(_h)], ctypes.c_int),
     "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, _i32p, ctypes.c_int32, _i32p,
@@ -236,6 +237,17 @@ def csrk_device_vals(h: int) -> int:
 
 def csrk_spmv(h: int, vals_dev, x_dev, y_dev, nrhs: int, stream):
     _check(lib().csrk_spmv(h, vals_dev, x_dev, y_dev, int(nrhs), stream), "csrk_spmv")
+
+
+def csrk_spmv_host(h: int, x, y=None, nthreads: int = 0):
+    """y' = A' x' on the host CPU; x (and y) float64 arrays of length n in permuted space."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if y is None:
+        y = np.empty_like(x)
+    if y.dtype != np.float64 or not y.flags.c_contiguous or y.shape != x.shape:
+        raise ValueError("y must be a contiguous float64 array shaped like x")
+    _check(lib().csrk_spmv_host(h, x.ctypes.data_as(_f64p), y.ctypes.data_as(_f64p), int(nthreads)), "csrk_spmv_host")
+    return y
 
 
 def csrk_spmv_plain(h: int, vals_dev, x_dev, y_dev, nrhs: int, stream):

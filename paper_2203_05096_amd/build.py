@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(OUT_DIR, "libcsrk.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "csrk")
 
-HOST_SOURCES = ["host/graph.cpp", "host/csr.cpp", "host/tune.cpp"]
+HOST_SOURCES = ["host/graph.cpp", "host/csr.cpp", "host/tune.cpp", "host/cpu_spmv.cpp"]
 HIP_SOURCES = ["device/kernels.hip", "capi.hip"]
 
 ARCH = os.environ.get("CSRK_OFFLOAD_ARCH", "gfx950")
@@ -28,7 +28,7 @@ CXX = os.environ.get("CXX_HOST", shutil.which("g++") or "g++")
 # Packed FP32 instructions are kept out of generated code on purpose.
 HIP_FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-Wall", "-Wno-unused-result", "-I", os.path.join(ROOT, "include")]
-HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-I", os.path.join(ROOT, "include")]
+HOST_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-fopenmp", "-Wall", "-I", os.path.join(ROOT, "include")]
 
 
 def _run(cmd):
@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
                 print(r.stdout + r.stderr, file=sys.stderr)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,
-          *[_obj(s) for s in HOST_SOURCES + HIP_SOURCES]])
+          *[_obj(s) for s in HOST_SOURCES + HIP_SOURCES], "-lgomp"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -295,6 +295,15 @@ csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out
     });
 }
 
+csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nthreads) {
+    return guard([&] {
+        if (!h || (!x && h->n > 0) || (!y && h->n > 0)) throw Error{CSRK_ERR_ARG, "null handle or vector"};
+        csrk::spmv_host(int64_t(h->ssr_ptr.size()) - 1, h->ssr_ptr.data(), h->sr_ptr.data(), h->row_ptr.data(),
+                        h->col_idx.data(), h->vals.data(), x, y, nthreads);
+        return CSRK_OK;
+    });
+}
+
 csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out) {
     return guard([&] {
         if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
@@ -317,7 +326,8 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
         csrk_params q = resolve_params(n, nnz, p);
         csrk::Grouping gr;
         if (q.reorder == CSRK_REORDER_BANDK) {
-            gr = csrk::bandk(n, row_ptr, col_idx, q.srs, q.ssrs);
+            gr = q.k == 2 ? csrk::bandk2(n, row_ptr, col_idx, q.srs, q.ssrs)
+                          : csrk::bandk(n, row_ptr, col_idx, q.srs, q.ssrs);
         } else if (q.reorder == CSRK_REORDER_RCM) {
             gr = csrk::rcm_chunked(n, row_ptr, col_idx, q.srs, q.ssrs);
         } else {

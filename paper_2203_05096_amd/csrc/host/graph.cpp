@@ -248,6 +248,30 @@ Grouping bandk(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_
     return r;
 }
 
+Grouping bandk2(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t group) {
+    if (srs < 1 || group < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
+    Grouping r;
+    if (n == 0) {
+        r.sr_ptr = {0};
+        r.ssr_ptr = {0};
+        return r;
+    }
+    Graph g0 = graph_from_csr(n, row_ptr, col_idx);
+    Aggregation a1 = aggregate(g0, srs);
+    Graph g1 = quotient(g0, a1);
+    std::vector<int32_t> order1 = cuthill_mckee(g1);
+    std::reverse(order1.begin(), order1.end());
+    r.perm = expand(g0, order1, a1);
+    std::vector<int64_t> srsz, ssrsz;
+    srsz.reserve(order1.size());
+    for (int32_t s : order1) srsz.push_back(a1.child_ptr[s + 1] - a1.child_ptr[s]);
+    const int64_t nsr = static_cast<int64_t>(srsz.size());
+    for (int64_t t = 0; t * group < nsr; ++t) ssrsz.push_back(std::min<int64_t>(group, nsr - t * group));
+    r.sr_ptr = running(srsz);
+    r.ssr_ptr = running(ssrsz);
+    return r;
+}
+
 Grouping chunked(std::vector<int32_t> perm, int32_t srs, int32_t ssrs) {
     if (srs < 1 || ssrs < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
     Grouping r;

@@ -78,6 +78,11 @@ struct Grouping {
 // reverse Cuthill-McKee of the coarsest graph, expand twice.
 Grouping bandk(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t ssrs);
 
+// Band-k with k = 2 (CSR-2): coarsen once by SRS, reverse Cuthill-McKee of the
+// coarse graph, expand.  The format has no super-super-row level; for the GPU
+// launch the super-rows are grouped `group` at a time in order (ssr_ptr).
+Grouping bandk2(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t group);
+
 // Fixed-size chunks over a given order (input order or RCM of G0).
 Grouping chunked(std::vector<int32_t> perm, int32_t srs, int32_t ssrs);
 Grouping rcm_chunked(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t ssrs);
@@ -129,6 +134,13 @@ struct Stats {
 };
 Stats row_stats(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, bool sorted_rows);
 int32_t bandwidth(int32_t n, const int32_t *row_ptr, const int32_t *col_idx);
+
+// ---------------------------------------------------------------- CPU kernel
+
+// y = A' x on the host: super-super-rows in parallel (OpenMP, static
+// schedule), rows summed left to right (Section 2.2 listing).
+void spmv_host(int64_t nssr, const int32_t *ssr_ptr, const int32_t *sr_ptr, const int32_t *row_ptr,
+               const int32_t *col_idx, const double *vals, const double *x, double *y, int nthreads);
 
 // ---------------------------------------------------------------- model
 

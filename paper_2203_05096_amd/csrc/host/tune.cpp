@@ -126,7 +126,7 @@ csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
 }
 
 void check_params(const csrk_params &p) {
-    if (p.k != 3) throw Error{CSRK_ERR_ARG, "only k = 3 is supported"};
+    if (p.k != 2 && p.k != 3) throw Error{CSRK_ERR_ARG, "k must be 2 or 3"};
     if (p.srs < 1 || p.ssrs < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
     const int L = p.lanes_per_row;
     if (L < 1 || L > 64 || (L & (L - 1))) throw Error{CSRK_ERR_ARG, "lanes_per_row must be a power of two in 1..64"};

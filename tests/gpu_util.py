@@ -13,8 +13,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def params(srs, ssrs, lanes=1, waves=4, reorder="bandk"):
-    return {"k": 3, "srs": int(srs), "ssrs": int(ssrs), "lanes_per_row": int(lanes), "waves_per_wg": int(waves),
+def params(srs, ssrs, lanes=1, waves=4, reorder="bandk", k=3):
+    return {"k": int(k), "srs": int(srs), "ssrs": int(ssrs), "lanes_per_row": int(lanes), "waves_per_wg": int(waves),
             "reorder": reorder}
 
 

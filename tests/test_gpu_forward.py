@@ -75,6 +75,40 @@ def test_random_ragged_all_precisions(store, reorder):
         check_forward(y, A, xr, perm, "f32", False, vals=vals_stored, label=f"{store} {reorder} (stored values)")
 
 
+@pytest.mark.parametrize("store", ["f64", "f32"])
+def test_csr2_forward_and_adjoint(store):
+    """k = 2 (one grouping level): same kernels over the CSR-2 structure."""
+    from oracle import adjoint as OA
+    A = random_sparse(4001, 7.0, seed=19, empty_row_frac=0.05, symmetric_pattern=False)
+    rng = np.random.default_rng(20)
+    x, g = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    if store != "f64":
+        A.vals = OP.stored_values(A.vals, store)
+        x, g = x.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    for p in (params(24, 2, lanes=2, waves=2, k=2), params(64, 4, lanes=1, waves=4, k=2)):
+        say("csr2", store, p)
+        M = _build(A, store, p)
+        assert M.info["params"]["k"] == 2
+        y, perm = _run(M, x)
+        check_forward(y, A, x, perm, store, False, label=f"csr2 {store}")
+        s = M.structure()
+        dt = VEC[store]
+        gx, gv = M.adjoint(to_dev(x[s["perm"]], dt), to_dev(g[s["perm"]], dt))
+        torch.cuda.synchronize()
+        gv_in = np.empty(A.nnz)
+        gv_in[s["vmap"]] = gv.double().cpu().numpy()
+        ref = OA.grad_vals(A.row_ptr, A.col_idx, x, g)
+        if store != "f64":
+            ref = ref.astype(np.float32).astype(np.float64)
+        assert np.array_equal(gv_in, ref)
+        gx_in = np.empty(A.n)
+        gx_in[s["perm"]] = gx.double().cpu().numpy()
+        gref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, g)
+        scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(g))
+        tol = 1e-12 if store == "f64" else 1e-5
+        assert np.all(np.abs(gx_in - gref) <= tol * scale)
+
+
 def test_long_rows_exceed_staging_window():
     # rows of 3000 nonzeros (longer than a wavefront's LDS window) next to short rows
     n = 4000

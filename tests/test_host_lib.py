@@ -86,21 +86,21 @@ def _path(n):
     return np.array(rp), np.array(ci)
 
 
-def _params(srs, ssrs, reorder="bandk"):
-    return {"k": 3, "srs": srs, "ssrs": ssrs, "lanes_per_row": 1, "waves_per_wg": 4, "reorder": reorder}
+def _params(srs, ssrs, reorder="bandk", k=3):
+    return {"k": k, "srs": srs, "ssrs": ssrs, "lanes_per_row": 1, "waves_per_wg": 4, "reorder": reorder}
 
 
-def _lib_structure(row_ptr, col_idx, vals, srs, ssrs, reorder="bandk"):
-    h = C.csrk_build_host(row_ptr, col_idx, vals, _params(srs, ssrs, reorder))
+def _lib_structure(row_ptr, col_idx, vals, srs, ssrs, reorder="bandk", k=3):
+    h = C.csrk_build_host(row_ptr, col_idx, vals, _params(srs, ssrs, reorder, k))
     try:
         return C.csrk_copy_structure(h), C.csrk_get_info(h)
     finally:
         C.csrk_destroy(h)
 
 
-def _assert_same_as_oracle(A_rp, A_ci, A_vals, srs, ssrs, reorder="bandk"):
-    s, info = _lib_structure(A_rp, A_ci, A_vals, srs, ssrs, reorder)
-    perm, sr_ptr, ssr_ptr = OB.build_grouping(A_rp, A_ci, srs, ssrs, reorder)
+def _assert_same_as_oracle(A_rp, A_ci, A_vals, srs, ssrs, reorder="bandk", k=3):
+    s, info = _lib_structure(A_rp, A_ci, A_vals, srs, ssrs, reorder, k)
+    perm, sr_ptr, ssr_ptr = OB.build_grouping(A_rp, A_ci, srs, ssrs, reorder, k)
     rp2, ci2, v2, vmap = OB.apply_permutation(A_rp, A_ci, A_vals, perm)
     assert np.array_equal(s["perm"], perm)
     assert np.array_equal(s["sr_ptr"], sr_ptr)
@@ -198,6 +198,21 @@ def test_bitexact_irregular_budget_split(reorder, symmetric):
     A = rmat_matrix(13, 6.0, 17, symmetric=symmetric)
     s, info = _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 64, 4, reorder)
     assert info["nsr"] > -(-A.n // 64)  # at least one super-row was split
+
+
+@pytest.mark.parametrize("seed,sym,srs,group", [(0, True, 4, 3), (1, False, 8, 2), (3, True, 1, 1),
+                                                (6, False, 64, 8), (7, True, 2, 64)])
+def test_bitexact_csr2(seed, sym, srs, group):
+    A = random_sparse(400, 4.0, seed=seed, empty_row_frac=0.1, symmetric_pattern=sym)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, srs, group, k=2)
+
+
+def test_bitexact_csr2_irregular_and_3d():
+    from gen.irregular import rmat_matrix
+    A = rmat_matrix(12, 6.0, 4, symmetric=False)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 32, 4, k=2)
+    L = laplacian((12, 11, 10), "3d7", 6.0)
+    _assert_same_as_oracle(L.row_ptr, L.col_idx, L.vals, 16, 2, k=2)
 
 
 def test_info_counts_long_rows():
@@ -355,3 +370,23 @@ def test_autotune_helpers_match_library_model():
         n = 100000
         p = C.csrk_tune(n, int(round(r * n)), "mi355x")
         assert p["lanes_per_row"] == T.lanes_rule(int(round(r * n)) / n), r
+
+
+def test_spmv_host_matches_oracle_bitwise():
+    """The CPU kernel sums each row left to right, as the oracle does: bitwise equal results."""
+    from oracle import spmv as OS
+    from gen.irregular import rmat_matrix
+    for A, p in ((random_sparse(3000, 6.0, seed=41, empty_row_frac=0.1), _params(16, 4)),
+                 (rmat_matrix(12, 4.0, 5), _params(32, 2)),
+                 (random_sparse(500, 3.0, seed=42), _params(8, 3, k=2))):
+        h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
+        try:
+            s = C.csrk_copy_structure(h)
+            x = np.random.default_rng(43).uniform(-1, 1, A.n)
+            for threads in (1, 3, 0):
+                y = C.csrk_spmv_host(h, x[s["perm"]], nthreads=threads)
+                ref = OS.spmv(s["row_ptr"], s["col_idx"], s["vals"], x[s["perm"]])
+                assert np.array_equal(y.view(np.uint64), ref.view(np.uint64))
+        finally:
+            C.csrk_destroy(h)
+    assert C.STATUS[C.lib().csrk_spmv_host(None, None, None, 0)] == "CSRK_ERR_ARG"

@@ -233,3 +233,32 @@ def test_balance_invariants_rmat(reorder):
         b = int(sr[s + 1])
         if b not in ends:
             assert sr_cost[s] + cost[b] > budget
+
+
+# ---------------------------------------------------------------- CSR-2 (k = 2)
+
+def test_csr2_worked_example_path12():
+    # Path 0-1-...-11, SRS 2: CM(G0) = 0..11 gives SRs {0,1} (id 0), {2,3} (id 2), ..., {10,11} (id 10); G1 is
+    # a path; RCM(G1) = 10, 8, ..., 0.  Expanding SR 10: row 11 first (degree 1), then 10; in SR 8 row 9 comes
+    # first (weight 1 to the emitted row 10), then 8; and so on.  Groups of 2 SRs for the launch.
+    rp, ci = _path(12)
+    perm, sr_ptr, ssr_ptr = B.bandk_k2(rp, ci, 2, 2)
+    assert perm.tolist() == list(range(11, -1, -1))
+    assert sr_ptr.tolist() == list(range(0, 13, 2)) and ssr_ptr.tolist() == [0, 2, 4, 6]
+
+
+def test_csr2_srs1_is_rcm_and_invariants():
+    A = random_sparse(300, 5.0, seed=8, symmetric_pattern=True)
+    perm, sr_ptr, ssr_ptr = B.bandk_k2(A.row_ptr, A.col_idx, 1, 3)
+    assert perm.tolist() == list(B.reverse_cuthill_mckee(B.graph_from_csr(A.row_ptr, A.col_idx)))
+    perm, sr_ptr, ssr_ptr = B.bandk_k2(A.row_ptr, A.col_idx, 7, 3)
+    assert sorted(perm.tolist()) == list(range(A.n))
+    assert sr_ptr[0] == 0 and sr_ptr[-1] == A.n and np.all(np.diff(sr_ptr) >= 1) and np.all(np.diff(sr_ptr) <= 7)
+    assert ssr_ptr[-1] == len(sr_ptr) - 1 and np.all(np.diff(ssr_ptr)[:-1] == 3)
+    x = np.random.default_rng(1).uniform(-1, 1, A.n)
+    rp2, ci2, v2, _ = B.apply_permutation(A.row_ptr, A.col_idx, A.vals, perm)
+    y2 = O.spmv(rp2, ci2, v2, x[perm])
+    y = np.empty(A.n)
+    y[perm] = y2
+    assert np.allclose(y, O.spmv(A.row_ptr, A.col_idx, A.vals, x), rtol=0, atol=1e-12)
+
