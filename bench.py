@@ -157,6 +157,32 @@ def cpu_baseline(mats, xs, gs, budget_s=12.0):
             "cpu": cpu_model()}
 
 
+def cg_study(torch, C, CsrkMatrix, A, b, rtol=1e-8):
+    """csrk_cg on the (symmetric positive definite) matrix with each value storage: iterations, solve time and
+    the final relative residual, both the solver's recurrence one and ||b - A x|| / ||b|| with the FP64
+    matrix (scipy.sparse product)."""
+    import scipy.sparse as sp
+    A64 = sp.csr_matrix((A.vals, A.col_idx, A.row_ptr), shape=(A.n, A.n))
+    out = {}
+    for store in ("f64", "f32", "bf16"):
+        M = CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, C.csrk_tune(A.n, A.nnz, "mi355x"), store), store)
+        perm = M.structure()["perm"]
+        bd = torch.from_numpy(np.ascontiguousarray(b[perm])).cuda()
+        M.cg(bd, rtol=1e-2, max_iter=5, check_every=5)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xd, it, rel = M.cg(bd, rtol=rtol, max_iter=20000, check_every=25)
+        ms = (time.perf_counter() - t0) * 1e3
+        x = np.empty(A.n)
+        x[perm] = xd.cpu().numpy()
+        true = float(np.linalg.norm(b - A64 @ x) / np.linalg.norm(b))
+        out[store] = {"iterations": it, "ms": round(ms, 2), "ms_per_iteration": round(ms / max(it, 1), 4),
+                      "recurrence_rel_residual": rel, "true_rel_residual_fp64_matrix": true}
+        M.close()
+    out["note"] = f"rtol {rtol}, b = the workload's x vector, x0 = 0, convergence checked every 25 iterations"
+    return out
+
+
 def cpu_csrk(C, A, x, W, reps=20):
     """The library's host CPU kernel (csrk_spmv_host, OpenMP over super-super-rows) on this matrix: the
     Band-k structure of the GPU handle, and plain CSR (one row per super-row, one super-row per
@@ -425,6 +451,8 @@ def main():
             extras["csr2_forward_us"] = round(k2 * 1e3, 2)
             M2.close()
             extras["cpu_csrk"] = cpu_csrk(C, A, x, W)
+            if args.workload == "c2":
+                extras["cg"] = cg_study(torch, C, CsrkMatrix, A, w["x"])
     if isinstance(W, Single):
         extras["accuracy"] = W.accuracy(torch, w["x"])
         log(f"accuracy {extras['accuracy']}")

@@ -241,6 +241,27 @@ csrk_status csrk_spmv_plain(csrk_handle h, const void *vals_dev, const void *x_d
 csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nthreads);
 
 /*
+ * csrk_cg — conjugate gradients for A' x' = b' (A' symmetric positive
+ * definite), the iterative-solver use the paper names for the format
+ * (Section 1 and the conclusions).  Each iteration is one CSR-k product in
+ * the handle's storage precision (FP32 copies of the direction vector feed
+ * FP32/BF16 storage) plus FP64 vector updates; x', r', p' and every
+ * reduction are FP64 and reduced in a fixed order, so the iteration is
+ * reproducible.  b_dev (n doubles) and x_dev (n doubles, the initial guess
+ * on entry, the solution on exit) are device arrays in permuted space.  Stops
+ * when ||r||_2 <= rtol * ||b||_2 (r the recurrence residual, checked every
+ * check_every iterations) or after max_iter iterations; *iters_out and
+ * *rel_resid_out (both may be NULL) receive the iteration count and
+ * ||r||_2 / ||b||_2.  Allocates 4 work vectors on the device for the call and
+ * synchronises `stream` before returning.  Errors: CSRK_ERR_ARG (null
+ * vectors, rtol <= 0, max_iter < 0, check_every < 1), CSRK_ERR_UNSUPPORTED on
+ * a breakdown (p'A p <= 0: the stored matrix is not positive definite),
+ * CSRK_ERR_ALLOC, CSRK_ERR_DEVICE.
+ */
+csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
+                    int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out);
+
+/*
  * csrk_spmv_adjoint — gradients of L = <g', A' x'> (not in the paper):
  * grad_x' = A'^T g' (n x nrhs, same type as x) and grad_vals'[k] =
  * sum_c g'[row(k), c] x'[col(k), c] (nnz values in CSR-k order, FP64 for F64

@@ -66,6 +66,8 @@ _SIGS = {
     "csrk_tune_rhs": ([ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int, ctypes.POINTER(csrk_params)],
                       ctypes.c_int),
     "csrk_spmv_host": ([_h, _f64p, _f64p, ctypes.c_int32], ctypes.c_int),
+    "csrk_cg": ([_h, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
+                 ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params),
                          ctypes.POINTER(_h)], ctypes.c_int),
     "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, _i32p, ctypes.c_int32, _i32p,
@@ -248,6 +250,15 @@ def csrk_spmv_host(h: int, x, y=None, nthreads: int = 0):
         raise ValueError("y must be a contiguous float64 array shaped like x")
     _check(lib().csrk_spmv_host(h, x.ctypes.data_as(_f64p), y.ctypes.data_as(_f64p), int(nthreads)), "csrk_spmv_host")
     return y
+
+
+def csrk_cg(h: int, b_dev, x_dev, rtol: float, max_iter: int, check_every: int, stream):
+    """Runs csrk_cg; returns (iterations, relative recurrence residual)."""
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    _check(lib().csrk_cg(h, b_dev, x_dev, float(rtol), int(max_iter), int(check_every), stream, ctypes.byref(it),
+                         ctypes.byref(rr)), "csrk_cg")
+    return it.value, rr.value
 
 
 def csrk_spmv_plain(h: int, vals_dev, x_dev, y_dev, nrhs: int, stream):

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <initializer_list>
 #include <cstdlib>
 #include <cstring>
@@ -516,6 +517,82 @@ csrk_status csrk_spmv(csrk_handle h, const void *vals_dev, const void *x_dev, vo
         hip_check(csrk::dev::spmv(arrays_of(h), h->store, v, x_dev, y_dev, nrhs, shape_of(h),
                                   static_cast<hipStream_t>(stream)),
                   "csrk_spmv launch");
+        return CSRK_OK;
+    });
+}
+
+// Device buffers of one CG solve, freed on every exit path.
+struct CgBuffers {
+    std::vector<void *> ptrs;
+    void *get(size_t bytes, const char *what) {
+        void *p = nullptr;
+        hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), what);
+        ptrs.push_back(p);
+        return p;
+    }
+    ~CgBuffers() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+};
+
+csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
+                    int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out) {
+    return guard([&] {
+        need_device(h);
+        if (!b_dev || !x_dev || !(rtol > 0) || max_iter < 0 || check_every < 1)
+            throw Error{CSRK_ERR_ARG, "need b, x, rtol > 0, max_iter >= 0, check_every >= 1"};
+        check_vec(b_dev, h, "b");
+        check_vec(x_dev, h, "x");
+        DeviceScope ds(h->device);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const int64_t n = h->n;
+        const bool lo = h->store != CSRK_F64;  // product vectors are FP32
+        const csrk::dev::Arrays a = arrays_of(h);
+        const csrk::dev::Shape shp = shape_of(h);
+        CgBuffers buf;
+        double *r = static_cast<double *>(buf.get(size_t(n) * 8, "cg r"));
+        double *p = static_cast<double *>(buf.get(size_t(n) * 8, "cg p"));
+        void *q = buf.get(size_t(n) * (lo ? 4 : 8), "cg q");
+        float *p_lo = lo ? static_cast<float *>(buf.get(size_t(n) * 4, "cg p (fp32)")) : nullptr;
+        double *part = static_cast<double *>(buf.get(csrk::dev::kCgGrid * 8, "cg partial sums"));
+        double *s = static_cast<double *>(buf.get(8 * 8, "cg scalars"));
+        auto spmv = [&](const void *in) {
+            hip_check(csrk::dev::spmv(a, h->store, h->d_vals, in, q, 1, shp, st), "cg product");
+        };
+        // r = b - A x0, p = r, rr = r . r, bb = b . b
+        if (lo) hip_check(csrk::dev::cg_round(x_dev, p_lo, n, st), "cg round");
+        spmv(lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(x_dev));
+        hip_check(csrk::dev::cg_residual(b_dev, q, lo, r, n, part, s, st), "cg residual");
+        hip_check(csrk::dev::cg_norm2(b_dev, n, part, s, st), "cg norm");
+        hip_check(csrk::dev::cg_set_p(r, p, p_lo, s, n, false, st), "cg p");
+        double host_s[6] = {0, 0, 0, 0, 0, 0};
+        auto read_scalars = [&]() {
+            hip_check(hipMemcpyAsync(host_s, s, sizeof(host_s), hipMemcpyDeviceToHost, st), "cg read");
+            hip_check(hipStreamSynchronize(st), "cg sync");
+        };
+        read_scalars();
+        const double bnorm = std::sqrt(host_s[5]);
+        const double target = rtol * (bnorm > 0 ? bnorm : 1.0);
+        int32_t it = 0;
+        bool done = std::sqrt(host_s[0]) <= target;
+        while (!done && it < max_iter) {
+            spmv(lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(p));
+            hip_check(csrk::dev::cg_alpha(p, q, lo, n, part, s, st), "cg alpha");
+            hip_check(csrk::dev::cg_step(x_dev, r, p, q, lo, n, part, s, st), "cg step");
+            hip_check(csrk::dev::cg_set_p(r, p, p_lo, s, n, true, st), "cg p");
+            ++it;
+            if (it % check_every == 0 || it == max_iter) {
+                read_scalars();
+                if (!(host_s[1] > 0) || !std::isfinite(host_s[0]))
+                    throw Error{CSRK_ERR_UNSUPPORTED,
+                                "CG breakdown (p'Ap <= 0 or a non-finite residual): the matrix is not symmetric "
+                                "positive definite in the stored precision"};
+                done = std::sqrt(host_s[0]) <= target;
+            }
+        }
+        if (iters_out) *iters_out = it;
+        if (rel_resid_out) *rel_resid_out = std::sqrt(host_s[0]) / (bnorm > 0 ? bnorm : 1.0);
+        hip_check(hipStreamSynchronize(st), "cg sync");
         return CSRK_OK;
     });
 }

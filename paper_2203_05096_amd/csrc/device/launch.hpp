@@ -106,5 +106,26 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint);
 
+// Conjugate-gradient vector kernels (device/cg.hip).  FP64 vectors; q (the
+// product's output) is FP32 when q_f32.  part holds kCgGrid partial sums; s
+// the scalars rr, pq, alpha, beta, rr_new, bb at s[0..5].
+constexpr int kCgGrid = 1024;
+int cg_grid(int64_t n);
+// r = b - q, s[0] = r . r
+hipError_t cg_residual(const double *b, const void *q, bool q_f32, double *r, int64_t n, double *part, double *s,
+                       hipStream_t st);
+// s[5] = b . b
+hipError_t cg_norm2(const double *b, int64_t n, double *part, double *s, hipStream_t st);
+// p = r + beta p (p = r when !use_beta); p_lo = float(p) when p_lo != NULL
+hipError_t cg_set_p(const double *r, double *p, float *p_lo, const double *s, int64_t n, bool use_beta,
+                    hipStream_t st);
+// s[1] = p . q, s[2] = alpha = s[0] / s[1]
+hipError_t cg_alpha(const double *p, const void *q, bool q_f32, int64_t n, double *part, double *s, hipStream_t st);
+// x += alpha p, r -= alpha q, s[4] = r . r, s[3] = beta = s[4] / s[0], s[0] = s[4]
+hipError_t cg_step(double *x, double *r, const double *p, const void *q, bool q_f32, int64_t n, double *part,
+                   double *s, hipStream_t st);
+// out = float(v)
+hipError_t cg_round(const double *v, float *out, int64_t n, hipStream_t st);
+
 }  // namespace dev
 }  // namespace csrk

@@ -109,6 +109,19 @@ class CsrkMatrix:
         C.csrk_spmv(self.handle, self._check_vals(vals), _ptr(x), _ptr(y), nrhs, _stream())
         return y
 
+    def cg(self, b: torch.Tensor, x0: torch.Tensor | None = None, rtol: float = 1e-8, max_iter: int = 10000,
+           check_every: int = 10):
+        """Conjugate gradients for A' x = b (permuted space, float64 device vectors); returns (x, iterations,
+        relative residual)."""
+        for t, name in ((b, "b"), (x0, "x0")):
+            if t is None:
+                continue
+            if t.device.type != "cuda" or t.dtype != torch.float64 or not t.is_contiguous() or t.shape != (self.n,):
+                raise TypeError(f"{name} must be a contiguous float64 CUDA vector of length {self.n}")
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        it, rel = C.csrk_cg(self.handle, _ptr(b), _ptr(x), rtol, max_iter, check_every, _stream())
+        return x, it, rel
+
     def spmv_plain(self, x, y=None, vals=None):
         """Same product with the plain CSR kernel (no super-row levels)."""
         nrhs = self._check_vec(x, "x")

@@ -152,3 +152,20 @@ def test_stencil_pattern_is_sorted_and_symmetric():
     for i in range(n):
         row = ci[rp[i]:rp[i + 1]]
         assert np.all(np.diff(row) > 0)
+
+
+def test_oracle_cg_against_dense_solve_and_finite_termination():
+    """CG on an n x n SPD system reaches the exact solution in at most n steps (exact arithmetic); in FP64 it
+    matches numpy.linalg.solve to rounding.  A planted sign error in the update would not converge."""
+    from gen import laplacian
+    from oracle import cg as OC
+    A = laplacian((5, 4), "2d5", 4.0)
+    D = np.zeros((A.n, A.n))
+    for i in range(A.n):
+        for k in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            D[i, A.col_idx[k]] += A.vals[k]
+    b = np.random.default_rng(3).uniform(-1, 1, A.n)
+    x, it, rel = OC.cg(A.row_ptr, A.col_idx, A.vals, b, rtol=1e-13, max_iter=4 * A.n)
+    assert it <= A.n + 2 and rel <= 1e-13
+    assert np.allclose(x, np.linalg.solve(D, b), rtol=0, atol=1e-11)
+    assert np.linalg.norm(D @ x - b) <= 1e-12 * np.linalg.norm(b) * 10
