@@ -100,6 +100,8 @@ typedef struct csrk_info {
     int32_t long_rows;        /* rows with more than CSRK_LONG_ROW nonzeros: each is computed
                                  by a workgroup of its own (Section 5.5 names computing
                                  dense rows in parallel as the fix for irregular matrices) */
+    int32_t values_symmetric; /* 1 when uploaded and A' equals A'^T exactly: the adjoint then
+                                 reads the forward's values instead of a transposed copy */
     csrk_params params;
 } csrk_info;
 
@@ -205,7 +207,12 @@ csrk_status csrk_copy_structure(csrk_handle h, int32_t *perm, int32_t *row_ptr, 
 
 /*
  * csrk_device_vals — the handle's device value array (nnz entries of the
- * storage type, CSR-k order, 16-byte aligned).  Owned by the handle.
+ * storage type, CSR-k order, 16-byte aligned).  Owned by the handle and
+ * meant to be read (e.g. copied as the initial value tensor): the adjoint
+ * with the handle's own values uses a transposed copy made at upload (or
+ * this same array when the matrix is symmetric), so values written here
+ * reach csrk_spmv but not csrk_spmv_adjoint; pass changed values to both
+ * calls through their vals_dev argument instead.
  */
 csrk_status csrk_device_vals(csrk_handle h, void **vals_dev);
 

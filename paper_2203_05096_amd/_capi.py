@@ -38,7 +38,8 @@ class csrk_info(ctypes.Structure):
                 ("rdensity", ctypes.c_double), ("row_variance", ctypes.c_double), ("max_row", ctypes.c_int32),
                 ("bandwidth_input", ctypes.c_int32), ("bandwidth", ctypes.c_int32), ("symmetry", ctypes.c_double),
                 ("max_sr_nnz", ctypes.c_int32), ("max_ssr_rows", ctypes.c_int32), ("on_device", ctypes.c_int32),
-                ("store", ctypes.c_int32), ("long_rows", ctypes.c_int32), ("params", csrk_params)]
+                ("store", ctypes.c_int32), ("long_rows", ctypes.c_int32), ("values_symmetric", ctypes.c_int32),
+                ("params", csrk_params)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "params"}

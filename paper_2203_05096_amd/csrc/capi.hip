@@ -40,6 +40,7 @@ struct csrk_matrix {
     std::vector<int32_t> long_rows, t_long_rows;
     int32_t *d_long = nullptr, *d_t_long = nullptr;
     csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
+    bool values_symmetric = false;  // A' == A'^T exactly: d_vals_t aliases d_vals
 };
 
 struct csrk_batch_s {
@@ -106,7 +107,7 @@ void free_device(csrk_matrix *h) {
     DeviceScope ds(h->device);
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
                     (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
-                    h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long})
+                    h->d_vals_t == h->d_vals ? nullptr : h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long})
         if (p) (void)hipFree(p);
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
     h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
@@ -405,13 +406,22 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
             if (!h->t_long_rows.empty()) h->d_t_long = upload_array(h->t_long_rows, "transposed long rows");
             h->split_fwd = xcd_split(h, h->row_ptr, nullptr);
             h->split_adj = h->trans.symmetric ? h->split_fwd : xcd_split(h, h->row_ptr, &h->trans.t_row_ptr);
+            // A symmetric matrix (pattern and values) is its own transpose: the
+            // adjoint then reads the values the forward reads, instead of a copy.
+            h->values_symmetric = h->trans.symmetric;
+            for (int64_t k = 0; h->values_symmetric && k < h->nnz; ++k)
+                h->values_symmetric = h->vals[size_t(k)] == h->vals[size_t(h->trans.t_src[size_t(k)])];
             hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
-            hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
+            if (h->values_symmetric)
+                h->d_vals_t = h->d_vals;
+            else
+                hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
             h->on_device = true;
             if (h->nnz > 0) {
                 double *tmp = upload_array(h->vals, "vals (staging)");
                 hipError_t e = csrk::dev::convert_values(tmp, h->d_vals, h->nnz, store, nullptr);
-                if (e == hipSuccess) e = csrk::dev::transpose_values(arrays_of(h), store, h->d_vals, h->d_vals_t, nullptr);
+                if (e == hipSuccess && !h->values_symmetric)
+                    e = csrk::dev::transpose_values(arrays_of(h), store, h->d_vals, h->d_vals_t, nullptr);
                 hipError_t e2 = hipDeviceSynchronize();
                 (void)hipFree(tmp);
                 hip_check(e, "value conversion");
@@ -471,6 +481,7 @@ csrk_status csrk_get_info(csrk_handle h, csrk_info *out) {
         i.on_device = h->on_device ? 1 : 0;
         i.store = h->store;
         i.long_rows = static_cast<int32_t>(long_rows_of(h->row_ptr).size());
+        i.values_symmetric = h->on_device && h->values_symmetric ? 1 : 0;
         i.params = h->params;
         *out = i;
         return CSRK_OK;

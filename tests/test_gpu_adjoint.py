@@ -242,3 +242,20 @@ def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
     ref = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
     scale = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
     assert np.all(np.abs(gv - ref) <= OP.gamma(nrhs, 2.0 ** -24) * scale)
+
+
+def test_symmetric_values_share_the_forward_array():
+    """A matrix equal to its transpose keeps one value array: info reports it, and the adjoint is unchanged."""
+    from gen import laplacian
+    L = laplacian((20, 18, 9), "3d7", 6.0)
+    L.vals = L.vals.copy()
+    L.vals[L.vals < 0] = -1.25  # still symmetric
+    M = _build(L, "f64", params(16, 4))
+    assert M.info["values_symmetric"] == 1
+    rng = np.random.default_rng(71)
+    x, g = rng.uniform(-1, 1, L.n), rng.uniform(-1, 1, L.n)
+    gx, gv = _adjoint(M, x, g)
+    assert np.array_equal(gv, OA.grad_vals(L.row_ptr, L.col_idx, x, g))
+    _check_grad_x(gx, L, g, "f64", False, "symmetric values")
+    A = random_sparse(800, 6.0, seed=72, symmetric_pattern=True)  # symmetric pattern, random values
+    assert _build(A, "f64", params(16, 4)).info["values_symmetric"] == 0
