@@ -67,11 +67,12 @@ struct Store<uint16_t> {
     __device__ static float widen(uint16_t v) { return bf16_to_f32(v); }
 };
 
-// Super-super-row of this workgroup under the work-balanced XCD ranges, or -1
-// for a padding block.
-__device__ __forceinline__ int32_t ssr_of_block(const XcdSplit &sp) {
-    const int32_t xcd = int32_t(blockIdx.x) % kXcds;
-    const int32_t t = sp.b[xcd] + int32_t(blockIdx.x) / kXcds;
+// Super-super-row of block b under the work-balanced XCD ranges, or -1 for a
+// padding block.  b counts from the first SSR block, which the long-row blocks
+// in front of it (a multiple of 8 of them) leave on XCD 0.
+__device__ __forceinline__ int32_t ssr_of_block(const XcdSplit &sp, int32_t b) {
+    const int32_t xcd = b % kXcds;
+    const int32_t t = sp.b[xcd] + b / kXcds;
     return t < sp.b[xcd + 1] ? t : -1;
 }
 
@@ -149,9 +150,10 @@ __device__ __forceinline__ void load_vec(const VT *__restrict__ vals, const int3
 // loads of a window before the dependent gathers, as in the windowed path, and
 // keeps a running partial sum; the lanes are summed at the end.  Rows longer
 // than kLongRow are not left to one wavefront at all: they are listed at
-// upload and split over the 16 wavefronts of a workgroup of their own
-// (k_long_forward / k_long_adjoint), which the paper names as the way to stop
-// very dense rows from being computed serially (Section 5.5).
+// upload and each is split over the wavefronts of a workgroup of its own, in
+// front of the super-super-row workgroups of the same launch; the paper names
+// computing very dense rows in parallel as the fix for irregular matrices
+// (Section 5.5).
 
 // Sum over entries [k0, k1) of value(k) * x[col(k)] (value(k) = vals[k], or
 // vals[src[k]] with IND) by one wavefront; every lane returns the sum.
@@ -364,7 +366,7 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
             // Row ra alone exceeds the staging window: stream it in windows, or
-            // leave it to the long-row kernel.
+            // leave it to the long-row workgroups.
             const int32_t re = uniform(__shfl(my_end, 0));
             if (!(skip_long && re - cs > kLongRow)) {
                 const A acc = range_dot<VT, IND>(cs, re, cols, src, vals, x, nnz, lane);
@@ -429,24 +431,108 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
     }
 }
 
+// ------------------------------------------------------------------ rows longer than kLongRow
+//
+// The main kernels leave rows longer than kLongRow to blocks of their own in
+// front of the SSR blocks of the same grid (so they start first and run
+// alongside the rest): the block's wavefronts take contiguous slices of the
+// row (slice lengths a multiple of the 16-byte load width), and the slices'
+// sums are added in slice order, so results do not depend on timing.
+
+template <int V>
+__device__ __forceinline__ void long_slice(int64_t k0, int64_t k1, int wave, int nw, int64_t &a, int64_t &b) {
+    const int64_t per = ((k1 - k0 + nw - 1) / nw + V - 1) / V * V;
+    a = min(k1, k0 + int64_t(wave) * per);
+    b = min(k1, a + per);
+}
+
+// Adds the wavefronts' partial sums in order; the result is valid in thread 0.
+template <typename A>
+__device__ __forceinline__ A block_total(A sum, unsigned char *smem, int wave, int nw, int lane) {
+    A *part = reinterpret_cast<A *>(smem);
+    if (lane == 0) part[wave] = sum;
+    __syncthreads();
+    A t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < nw; ++w) t += part[w];
+    return t;
+}
+
+// y[r] for long row r by the whole workgroup.
+template <typename VT>
+__device__ __forceinline__ void long_row_forward(int32_t r, const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ cols, const VT *__restrict__ vals,
+                                                 const typename Store<VT>::X *__restrict__ x,
+                                                 typename Store<VT>::X *__restrict__ y, int64_t nnz,
+                                                 unsigned char *smem, int wave, int nw, int lane) {
+    using A = typename Store<VT>::A;
+    int64_t a, b;
+    long_slice<Store<VT>::V>(row_ptr[r], row_ptr[r + 1], wave, nw, a, b);
+    const A sum = (a < b) ? range_dot<VT, false>(a, b, cols, nullptr, vals, x, nnz, lane) : A(0);
+    const A t = block_total(sum, smem, wave, nw, lane);
+    if (threadIdx.x == 0) y[r] = typename Store<VT>::X(t);
+}
+
+// Long-row item `item` of the adjoint: items [0, na) are long rows of A'
+// (grad_vals of the row, plus grad_x of the same row when `fused`), items
+// [na, na + nt) long rows of A'^T (grad_x only).
+template <typename VT, bool IND>
+__device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__restrict__ rows, int32_t na,
+                                                 const int32_t *__restrict__ t_rows, bool fused,
+                                                 const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
+                                                 const int32_t *__restrict__ t_row_ptr,
+                                                 const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src,
+                                                 const VT *__restrict__ valsT,
+                                                 const typename Store<VT>::X *__restrict__ x,
+                                                 const typename Store<VT>::X *__restrict__ g,
+                                                 typename Store<VT>::X *__restrict__ gx,
+                                                 typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                 unsigned char *smem, int wave, int nw, int lane) {
+    using A = typename Store<VT>::A;
+    const bool a_item = item < na;
+    const int32_t r = a_item ? rows[item] : t_rows[item - na];
+    const int32_t *rp = a_item ? row_ptr : t_row_ptr;
+    int64_t a, b;
+    long_slice<Store<VT>::V>(rp[r], rp[r + 1], wave, nw, a, b);
+    if (a_item && !fused) {
+        if (a < b) range_grad_vals<VT>(a, b, A(g[r]), cols, x, gv, nnz, lane);
+        return;  // uniform over the workgroup
+    }
+    A sum = 0;
+    if (a < b) {
+        if (a_item)
+            sum = range_adjoint<VT, IND>(a, b, A(g[r]), cols, t_src, valsT, x, g, gv, nnz, lane);
+        else
+            sum = range_dot<VT, IND>(a, b, t_col, t_src, valsT, g, nnz, lane);
+    }
+    const A t = block_total(sum, smem, wave, nw, lane);
+    if (threadIdx.x == 0) gx[r] = typename Store<VT>::X(t);
+}
+
 template <typename VT, int L>
 __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                                     typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                                    int skip_long, XcdSplit split) {
+                                                    const int32_t *__restrict__ long_rows, int32_t nlong,
+                                                    int32_t long_blocks, XcdSplit split) {
     using A = typename Store<VT>::A;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    const int32_t bid = int32_t(blockIdx.x);
+    if (bid < long_blocks) {
+        if (bid < nlong) long_row_forward<VT>(long_rows[bid], row_ptr, cols, vals, x, y, nnz, smem, wave, nw, lane);
+        return;
+    }
     A *buf = reinterpret_cast<A *>(smem + size_t(wave) * kStageBytes) + kStagePad;
-    const int32_t t = ssr_of_block(split);
+    const int32_t t = ssr_of_block(split, bid - long_blocks);
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_forward<VT, L, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y, nnz,
-                                 buf, lane, skip_long != 0);
+                                 buf, lane, true);
 }
 
 // LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
@@ -636,7 +722,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     unsigned char *lds = smem + size_t(wave) * kMrhsLds;
-    const int32_t t = ssr_of_block(split);
+    const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
@@ -936,7 +1022,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
         const int nrows = (~mask == 0ull) ? kWave : __builtin_ctzll(~mask);
         if (nrows == 0) {
             // Row ra alone exceeds the staging window: stream it in windows, or
-            // leave it to the long-row kernel.
+            // leave it to the long-row workgroups.
             const int32_t re = uniform(__shfl(my_end, 0));
             if (!(skip_long && re - cs > kLongRow)) {
                 const A acc = range_adjoint<VT, IND>(cs, re, A(g[ra]), cols, src, valsT, x, g, gv, nnz, lane);
@@ -1292,18 +1378,27 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
                                                        const typename Store<VT>::X *__restrict__ g,
                                                        typename Store<VT>::X *__restrict__ gx,
                                                        typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym,
-                                                       int skip_long, XcdSplit split) {
+                                                       const int32_t *__restrict__ long_rows, int32_t na,
+                                                       const int32_t *__restrict__ t_long_rows, int32_t nt,
+                                                       int32_t long_blocks, XcdSplit split) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
+    const int32_t bid = int32_t(blockIdx.x);
+    if (bid < long_blocks) {
+        if (bid < na + nt)
+            long_row_adjoint<VT, IND>(bid, long_rows, na, t_long_rows, sym != 0 && gx && gv, row_ptr, cols,
+                                      t_row_ptr, t_col, t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw, lane);
+        return;
+    }
     unsigned char *lds = smem + size_t(wave) * kAdjointLds;
-    const int32_t t = ssr_of_block(split);
+    const int32_t t = ssr_of_block(split, bid - long_blocks);
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
-                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane, skip_long != 0);
+                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane, true);
 }
 
 template <typename VT, int RL, int VX, bool IND>
@@ -1318,92 +1413,12 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     unsigned char *lds = smem + size_t(wave) * kMrhsLds;
-    const int32_t t = ssr_of_block(split);
+    const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
                                          t_src, valsT, x, g, gx, gv, nnz, nrhs, sym != 0, lds, lane);
-}
-
-// ------------------------------------------------------------------ long rows
-//
-// One workgroup of kLongWaves wavefronts per listed row: wavefront w takes the
-// w-th of kLongWaves contiguous slices of the row (slice lengths a multiple of
-// the 16-byte load width), and the slices' sums are added in slice order, so
-// results do not depend on timing.
-
-template <int V>
-__device__ __forceinline__ void long_slice(int64_t k0, int64_t k1, int wave, int64_t &a, int64_t &b) {
-    const int64_t per = ((k1 - k0 + kLongWaves - 1) / kLongWaves + V - 1) / V * V;
-    a = min(k1, k0 + int64_t(wave) * per);
-    b = min(k1, a + per);
-}
-
-template <typename VT>
-__global__ void __launch_bounds__(kLongWaves * kWave) k_long_forward(const int32_t *__restrict__ rows,
-                                                                     const int32_t *__restrict__ row_ptr,
-                                                                     const int32_t *__restrict__ cols,
-                                                                     const VT *__restrict__ vals,
-                                                                     const typename Store<VT>::X *__restrict__ x,
-                                                                     typename Store<VT>::X *__restrict__ y,
-                                                                     int64_t nnz) {
-    using A = typename Store<VT>::A;
-    using X = typename Store<VT>::X;
-    __shared__ A part[kLongWaves];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = uniform(threadIdx.x / kWave);
-    const int32_t r = rows[blockIdx.x];
-    int64_t a, b;
-    long_slice<Store<VT>::V>(row_ptr[r], row_ptr[r + 1], wave, a, b);
-    const A sum = (a < b) ? range_dot<VT, false>(a, b, cols, nullptr, vals, x, nnz, lane) : A(0);
-    if (lane == 0) part[wave] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        A t = 0;
-        for (int w = 0; w < kLongWaves; ++w) t += part[w];
-        y[r] = X(t);
-    }
-}
-
-// Items [0, na) are long rows of A' (rows): grad_vals of the row, plus grad_x
-// of the same row when `fused` (symmetric pattern, both outputs).  Items
-// [na, grid) are long rows of A'^T (t_rows): grad_x only.
-template <typename VT, bool IND>
-__global__ void __launch_bounds__(kLongWaves * kWave) k_long_adjoint(
-    const int32_t *__restrict__ rows, int32_t na, const int32_t *__restrict__ t_rows, int fused,
-    const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr,
-    const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src, const VT *__restrict__ valsT,
-    const typename Store<VT>::X *__restrict__ x, const typename Store<VT>::X *__restrict__ g,
-    typename Store<VT>::X *__restrict__ gx, typename Store<VT>::A *__restrict__ gv, int64_t nnz) {
-    using A = typename Store<VT>::A;
-    using X = typename Store<VT>::X;
-    __shared__ A part[kLongWaves];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = uniform(threadIdx.x / kWave);
-    const bool a_item = int32_t(blockIdx.x) < na;
-    const int32_t r = a_item ? rows[blockIdx.x] : t_rows[blockIdx.x - na];
-    const int32_t *rp = a_item ? row_ptr : t_row_ptr;
-    int64_t a, b;
-    long_slice<Store<VT>::V>(rp[r], rp[r + 1], wave, a, b);
-    A sum = 0;
-    if (a_item && !fused) {
-        if (a < b) range_grad_vals<VT>(a, b, A(g[r]), cols, x, gv, nnz, lane);
-        return;  // uniform over the workgroup
-    }
-    if (a < b) {
-        if (a_item)
-            sum = range_adjoint<VT, IND>(a, b, A(g[r]), cols, t_src, valsT, x, g, gv, nnz, lane);
-        else
-            sum = range_dot<VT, IND>(a, b, t_col, t_src, valsT, g, nnz, lane);
-    }
-    if (lane == 0) part[wave] = sum;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        A t = 0;
-        for (int w = 0; w < kLongWaves; ++w) t += part[w];
-        gx[r] = X(t);
-    }
 }
 
 // ------------------------------------------------------------------ plain CSR baseline
@@ -1648,14 +1663,11 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
         if (nrhs == 1) {
             return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
                 constexpr int L = decltype(lc)::value;
-                hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(a.split_fwd.width * kXcds), dim3(block),
+                const int32_t long_blocks = (a.nlong + kXcds - 1) / kXcds * kXcds;
+                hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(long_blocks + a.split_fwd.width * kXcds), dim3(block),
                                    size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
                                    static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
-                                   a.nnz, 1, a.split_fwd);
-                if (a.nlong > 0)
-                    hipLaunchKernelGGL((k_long_forward<VT>), dim3(a.nlong), dim3(kLongWaves * kWave), 0, st,
-                                       a.long_rows, a.row_ptr, a.col_idx, static_cast<const VT *>(vals),
-                                       static_cast<const X *>(x), static_cast<X *>(y), a.nnz);
+                                   a.nnz, a.long_rows, a.nlong, long_blocks, a.split_fwd);
                 return hipGetLastError();
             });
         }
@@ -1716,23 +1728,18 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
             if (nrhs == 1) {
                 return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
                     constexpr int LL = decltype(lc)::value;
-                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(a.split_adj.width * kXcds), dim3(block),
-                                       size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
-                                       a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
-                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       int(a.sym), 1, a.split_adj);
-                    // The rows the main kernel left out: long rows of A' for
-                    // grad_vals (and grad_x when fused), long rows of A'^T for
-                    // grad_x otherwise.
+                    // The long rows the main blocks leave out: long rows of A' for
+                    // grad_vals (and grad_x when fused), long rows of A'^T for grad_x
+                    // otherwise.
                     const bool fused = a.sym && gx && gv;
                     const int32_t na = (fused || gv) ? a.nlong : 0;
                     const int32_t nt = (!fused && gx) ? a.t_nlong : 0;
-                    if (na + nt > 0)
-                        hipLaunchKernelGGL((k_long_adjoint<VT, IND>), dim3(na + nt), dim3(kLongWaves * kWave), 0, st,
-                                           a.long_rows, na, a.t_long_rows, int(fused), a.row_ptr, a.col_idx,
-                                           a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
-                                           static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv),
-                                           a.nnz);
+                    const int32_t long_blocks = (na + nt + kXcds - 1) / kXcds * kXcds;
+                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(long_blocks + a.split_adj.width * kXcds),
+                                       dim3(block), size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                       a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
+                                       int(a.sym), a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj);
                     return hipGetLastError();
                 });
             }

@@ -12,13 +12,13 @@ namespace csrk {
 namespace dev {
 
 // Rows with more nonzeros than this are computed by a workgroup of their own
-// (split over kLongWaves wavefronts) instead of by their super-row's
-// wavefront; the handle lists them at upload.
+// (split over its wavefronts) instead of by their super-row's wavefront; the
+// handle lists them at upload.
 constexpr int32_t kLongRow = CSRK_LONG_ROW;
-constexpr int kLongWaves = 16;
 
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
-// by block index.  Block b runs super-super-row b[b % 8] + b / 8 of XCD b % 8's
+// by block index.  SSR block b (counted after the long-row blocks, a multiple
+// of 8 of them) runs super-super-row b[b % 8] + b / 8 of XCD b % 8's
 // contiguous range [b[x], b[x+1]); blocks past the end of their range exit at
 // once.  The ranges are cut so that each XCD gets about the same work.
 constexpr int kXcds = 8;

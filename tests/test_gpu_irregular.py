@@ -21,14 +21,17 @@ LONG_ROW = 1024  # rows longer than this get a workgroup of their own
 
 
 def _mixed(seed, symmetric, n=6000):
-    """Short rows (0..8 entries) mixed with rows of 509..520, 1023..1026, 3000 and 20000 entries."""
+    """Short rows (0..8 entries) mixed with rows of 509..520, 1023..1026, 3000 and 5000 entries, and a column
+    (7) present in every third row, so that A^T has a row of n / 3 entries too."""
     rng = np.random.default_rng(seed)
     special = {17: 509, 18: 510, 19: 511, 20: 520, 300: 1023, 301: 1024, 302: 1025, 303: 1026, 900: 3000,
-               2500: 20000 % n + 2000, 4000: 700}
+               2500: min(5000, n - 1), 4000 % n: 700}
     ii, jj = [], []
     for i in range(n):
         k = special.get(i, int(rng.integers(0, 9)))
         cols = rng.choice(n, size=min(k, n), replace=False)
+        if i % 3 == 0 and 7 not in cols:
+            cols = np.append(cols, 7)
         ii.extend([i] * len(cols))
         jj.extend(cols.tolist())
     ii, jj = np.array(ii, np.int64), np.array(jj, np.int64)
@@ -65,6 +68,8 @@ def test_mixed_matrix_has_every_row_class():
     lengths = np.diff(A.row_ptr)
     assert (lengths == 0).any() and ((lengths > 504) & (lengths <= LONG_ROW)).sum() >= 5
     assert (lengths == LONG_ROW).any() and (lengths > LONG_ROW).sum() >= 4
+    assert ((lengths > LONG_ROW) & (lengths <= 4096)).any() and (lengths > 4096).any()  # both long-row classes
+    assert np.bincount(A.col_idx, minlength=A.n).max() > 1024  # and a long row of A^T
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
