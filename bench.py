@@ -87,23 +87,28 @@ def cpu_model():
 
 
 def timed_launches(torch, fns, steps, warmup):
-    """Runs `steps` steps of the callables in `fns` after `warmup` steps; returns wall ms/step and per-fn
-    mean event ms (events on the current stream, which is the launch stream)."""
+    """Runs `warmup` untimed steps of the callables in `fns`, then exactly `steps` timed steps (wall clock,
+    bracketed by device synchronisation, no events inside), then `steps` more with an event pair around
+    every launch for the per-kernel means (events on the current stream, which is the launch stream).
+    Returns wall ms/step and per-fn mean event ms."""
     for _ in range(warmup):
         for f in fns:
             f()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for f in fns:
+            f()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
     ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
           for _ in fns]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for s in range(steps):
         for i, f in enumerate(fns):
             ev[i][s][0].record()
             f()
             ev[i][s][1].record()
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) * 1e3 / steps
     per = [float(np.mean([a.elapsed_time(b) for a, b in ev[i]])) for i in range(len(fns))]
     return wall, per
 
