@@ -474,11 +474,11 @@ __device__ __forceinline__ void long_row_forward(int32_t r, const int32_t *__res
 }
 
 // Long-row item `item` of the adjoint: items [0, na) are long rows of A'
-// (grad_vals of the row, plus grad_x of the same row when `fused`), items
-// [na, na + nt) long rows of A'^T (grad_x only).
-template <typename VT, bool IND>
+// (grad_vals of the row, plus grad_x of the same row when FUSED), items
+// [na, na + nt) long rows of A'^T (grad_x only; never with FUSED).
+template <typename VT, bool IND, bool FUSED>
 __device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__restrict__ rows, int32_t na,
-                                                 const int32_t *__restrict__ t_rows, bool fused,
+                                                 const int32_t *__restrict__ t_rows,
                                                  const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                  const int32_t *__restrict__ t_row_ptr,
                                                  const int32_t *__restrict__ t_col, const int32_t *__restrict__ t_src,
@@ -494,16 +494,15 @@ __device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__
     const int32_t *rp = a_item ? row_ptr : t_row_ptr;
     int64_t a, b;
     long_slice<Store<VT>::V>(rp[r], rp[r + 1], wave, nw, a, b);
-    if (a_item && !fused) {
-        if (a < b) range_grad_vals<VT>(a, b, A(g[r]), cols, x, gv, nnz, lane);
-        return;  // uniform over the workgroup
-    }
     A sum = 0;
-    if (a < b) {
-        if (a_item)
-            sum = range_adjoint<VT, IND>(a, b, A(g[r]), cols, t_src, valsT, x, g, gv, nnz, lane);
-        else
-            sum = range_dot<VT, IND>(a, b, t_col, t_src, valsT, g, nnz, lane);
+    if constexpr (FUSED) {
+        if (a < b) sum = range_adjoint<VT, IND>(a, b, A(g[r]), cols, t_src, valsT, x, g, gv, nnz, lane);
+    } else {
+        if (a_item) {
+            if (a < b) range_grad_vals<VT>(a, b, A(g[r]), cols, x, gv, nnz, lane);
+            return;  // uniform over the workgroup
+        }
+        if (a < b) sum = range_dot<VT, IND>(a, b, t_col, t_src, valsT, g, nnz, lane);
     }
     const A t = block_total(sum, smem, wave, nw, lane);
     if (threadIdx.x == 0) gx[r] = typename Store<VT>::X(t);
@@ -1367,7 +1366,7 @@ constexpr int kAdjointLds = kStageBytes + kStageEntries + 64 * 8;
 // LDS bytes per wavefront of the batched kernels (any direction, any nrhs).
 constexpr int kBatchLds = kMrhsLds > kAdjointLds ? kMrhsLds : kAdjointLds;
 
-template <typename VT, int L, bool IND>
+template <typename VT, int L, bool IND, bool FUSED>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                        const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ cols,
@@ -1388,17 +1387,27 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
     const int32_t bid = int32_t(blockIdx.x);
     if (bid < long_blocks) {
         if (bid < na + nt)
-            long_row_adjoint<VT, IND>(bid, long_rows, na, t_long_rows, sym != 0 && gx && gv, row_ptr, cols,
-                                      t_row_ptr, t_col, t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw, lane);
+            long_row_adjoint<VT, IND, FUSED>(bid, long_rows, na, t_long_rows, row_ptr, cols, t_row_ptr, t_col,
+                                             t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw, lane);
         return;
     }
     unsigned char *lds = smem + size_t(wave) * kAdjointLds;
     const int32_t t = ssr_of_block(split, bid - long_blocks);
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-    for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_adjoint<VT, L, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col, t_src,
-                               valsT, x, g, gx, gv, nnz, sym != 0, lds, lane, true);
+    // one instantiation per path keeps the other path's registers out of it
+    using A = typename Store<VT>::A;
+    for (int32_t s = s0 + wave; s < s1; s += nw) {
+        const int32_t r0 = uniform(sr_ptr[s]), r1 = uniform(sr_ptr[s + 1]);
+        if constexpr (FUSED) {
+            sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane, true);
+        } else {
+            if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
+            if (gx)
+                sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
+                                       reinterpret_cast<A *>(lds) + kStagePad, lane, true);
+        }
+    }
 }
 
 template <typename VT, int RL, int VX, bool IND>
@@ -1735,11 +1744,20 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                     const int32_t na = (fused || gv) ? a.nlong : 0;
                     const int32_t nt = (!fused && gx) ? a.t_nlong : 0;
                     const int32_t long_blocks = (na + nt + kXcds - 1) / kXcds * kXcds;
-                    hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND>), dim3(long_blocks + a.split_adj.width * kXcds),
-                                       dim3(block), size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
-                                       a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
-                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       int(a.sym), a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj);
+                    auto go = [&](auto fc) {
+                        constexpr bool F = decltype(fc)::value;
+                        hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F>),
+                                           dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
+                                           size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                           a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                           static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv),
+                                           a.nnz, int(a.sym), a.long_rows, na, a.t_long_rows, nt, long_blocks,
+                                           a.split_adj);
+                    };
+                    if (fused)
+                        go(std::true_type{});
+                    else
+                        go(std::false_type{});
                     return hipGetLastError();
                 });
             }
