@@ -14,7 +14,7 @@ of stdout).
 Other workloads: c3 = 3D 27-point 100^3 (precision study), c4 = 2D 9-point
 2048^2 with 10% of off-diagonals dropped (nonsymmetric, FP32), c5 = 64 3D
 7-point Laplacians of uneven size with 8 right-hand sides each, in one
-persistent batched launch per direction (FP32), irr = an R-MAT graph of 2^20
+batched launch per direction (FP32), irr = an R-MAT graph of 2^20
 rows (power-law row lengths, the paper's irregular class; FP64).
 """
 
@@ -296,7 +296,7 @@ class Single:
 
 
 class Batch:
-    """Many CSR-k matrices with blocks of right-hand sides in one persistent launch (workload c5)."""
+    """Many CSR-k matrices with blocks of right-hand sides in one launch (workload c5)."""
 
     def __init__(self, torch, C, CsrkMatrix, CsrkBatch, mats, xs, gs, store, nrhs):
         import concurrent.futures as cf

@@ -294,7 +294,7 @@ csrk_status csrk_destroy(csrk_handle h);
 
 /*
  * Batched forms (not in the paper): many matrices of uneven size, each with
- * an n_b x nrhs block, in one persistent launch over a work list of
+ * an n_b x nrhs block, in one launch over a work list of
  * (matrix, super-super-row) items.  All handles must be on the device with
  * the same storage type; they must outlive the batch.  The batch owns the
  * work list and a device pointer table.

@@ -115,10 +115,12 @@ def time_step(M: CsrkMatrix, x, g, y, gx, gv, reps: int = 20, warmup: int = 5) -
 
 def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes_list=LANES_SWEEP,
           waves_list=WAVES_SWEEP, reorder: str = "bandk", nrhs: int = 1, reps: int = 40, seed: int = 0,
-          name: str | None = None, threads: int = 8, objective: str = "forward") -> SweepResult:
+          name: str | None = None, threads: int = 8, objective: str = "forward", on_trial=None) -> SweepResult:
     """Times every combination on matrix A (an object with row_ptr, col_idx, vals).  objective is
     "forward" (the paper's) or "step" (forward + adjoint); waves_list None ties the waves per
-    workgroup to SSRS."""
+    workgroup to SSRS.  on_trial(M, x, y, trial), if given, is called after each timing with the
+    matrix and the permuted-space input and output of its last timed product (a caller's check
+    that every candidate computes the same product)."""
     n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
     res = SweepResult(name or getattr(A, "name", "matrix"), n, nnz, nnz / max(n, 1))
     dt = torch.float64 if store == "f64" else torch.float32
@@ -146,6 +148,9 @@ def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes
                 us = time_forward(M, x, y, reps) if objective == "forward" else \
                     time_step(M, x, gvec, y, gx, gv, reps)
                 res.trials.append(Trial(srs, ssrs, lanes, waves, reorder, us))
+                if on_trial is not None:
+                    torch.cuda.synchronize()
+                    on_trial(M, x, y, res.trials[-1])
             M.close()
     return res
 

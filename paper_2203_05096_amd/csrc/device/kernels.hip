@@ -535,8 +535,19 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
 }
 
 // LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
-// (value, column) pairs.
+// (value, column) pairs, or (value, column, grad_vals) triples of 4-byte
+// values in the fused adjoint; sized for the largest.
 constexpr int kMrhsLds = kStageEntries * (8 + 4);
+// The multi-column forward needs only its own storage type's pairs.
+template <typename VT>
+__host__ __device__ constexpr int mrhs_forward_lds() {
+    return kStageEntries * int(sizeof(typename Store<VT>::A) + sizeof(int32_t));
+}
+// LDS bytes per wavefront of the batched forward.
+template <typename VT>
+__host__ __device__ constexpr int batch_forward_lds(int nrhs) {
+    return nrhs == 1 ? kStageBytes : mrhs_forward_lds<VT>();
+}
 
 // VX consecutive right-hand-side columns starting at p (16-byte aligned when VX > 1).
 template <typename X, int VX>
@@ -720,7 +731,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    unsigned char *lds = smem + size_t(wave) * kMrhsLds;
+    unsigned char *lds = smem + size_t(wave) * mrhs_forward_lds<VT>();
     const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
@@ -1519,7 +1530,7 @@ __global__ void k_copy_f64(const double *__restrict__ src, double *__restrict__ 
 
 // ------------------------------------------------------------------ batched
 
-// Persistent batched forward: logical block b takes the contiguous item range
+// Batched forward: logical block b takes the contiguous item range
 // [b*per, (b+1)*per) of the (matrix, SSR) work list; logical indices are laid
 // out so each XCD owns a contiguous part of the list.  L is the lanes per row
 // (single right-hand side) or per row group (several: L lanes x VX columns).
@@ -1532,7 +1543,7 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    unsigned char *lds = smem + size_t(wave) * kBatchLds;
+    unsigned char *lds = smem + size_t(wave) * batch_forward_lds<VT>(nrhs);
     const int32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t per = (nitems + gridDim.x - 1) / gridDim.x;
     const int32_t i0 = b * per, i1 = min(nitems, i0 + per);
@@ -1686,7 +1697,7 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
             return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                 constexpr int RL = decltype(rc)::value;
                 hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, RL, VX>), dim3(a.split_fwd.width * kXcds), dim3(block),
-                                   size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                   size_t(s.waves) * mrhs_forward_lds<VT>(), st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
                                    static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
                                    a.nnz, nrhs, a.split_fwd);
                 return hipGetLastError();
@@ -1828,23 +1839,35 @@ hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtyp
     return hipGetLastError();
 }
 
+namespace {
+
+// Calls f(VT{}, integral_constant<VX>, integral_constant<L>) with the
+// instantiation the batched kernels use for this storage type, column count
+// and launch shape (the same choice for the launch and its occupancy query).
+template <typename F>
+hipError_t by_batch_shape(csrk_dtype store, int nrhs, const Shape &s, bool vec, F &&f) {
+    return by_dtype(store, [&](auto vt) -> hipError_t {
+        using X = typename Store<decltype(vt)>::X;
+        const int vx = (nrhs > 1 && vec && nrhs % (16 / int(sizeof(X))) == 0) ? 16 / int(sizeof(X)) : 1;
+        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+            return by_lanes(nrhs == 1 ? s.lanes_per_row : rhs_lanes(nrhs, decltype(vc)::value),
+                            [&](auto lc) -> hipError_t { return f(vt, vc, lc); });
+        });
+    });
+}
+
+}  // namespace
+
 hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
                          Shape s, int grid, bool vec, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    return by_dtype(store, [&](auto vt) -> hipError_t {
+    return by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
-        using X = typename Store<VT>::X;
-        const int vx = (nrhs > 1 && vec && nrhs % (16 / int(sizeof(X))) == 0) ? 16 / int(sizeof(X)) : 1;
-        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
-            constexpr int VX = decltype(vc)::value;
-            return by_lanes(nrhs == 1 ? s.lanes_per_row : rhs_lanes(nrhs, VX), [&](auto lc) -> hipError_t {
-                constexpr int LL = decltype(lc)::value;
-                hipLaunchKernelGGL((k_batch_forward<VT, LL, VX>), dim3(grid), dim3(block), size_t(s.waves) * kBatchLds,
-                                   st, descs, items, nitems, nrhs);
-                return hipGetLastError();
-            });
-        });
+        constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
+        hipLaunchKernelGGL((k_batch_forward<VT, LL, VX>), dim3(grid), dim3(block),
+                           size_t(s.waves) * batch_forward_lds<VT>(nrhs), st, descs, items, nitems, nrhs);
+        return hipGetLastError();
     });
 }
 
@@ -1852,39 +1875,35 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
                          Shape s, int grid, bool ind, bool vec, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    return by_dtype(store, [&](auto vt) -> hipError_t {
+    const size_t lds = size_t(s.waves) * kBatchLds;
+    return by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
-        using X = typename Store<VT>::X;
-        const int vx = (nrhs > 1 && vec && nrhs % (16 / int(sizeof(X))) == 0) ? 16 / int(sizeof(X)) : 1;
-        return by_vx<X>(vx, [&](auto vc) -> hipError_t {
-            constexpr int VX = decltype(vc)::value;
-            return by_lanes(nrhs == 1 ? s.lanes_per_row : rhs_lanes(nrhs, VX), [&](auto lc) -> hipError_t {
-                constexpr int LL = decltype(lc)::value;
-                const size_t lds = size_t(s.waves) * kBatchLds;
-                if (ind)
-                    hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, true>), dim3(grid), dim3(block), lds, st, descs,
-                                       items, nitems, nrhs);
-                else
-                    hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, false>), dim3(grid), dim3(block), lds, st, descs,
-                                       items, nitems, nrhs);
-                return hipGetLastError();
-            });
-        });
+        constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
+        if (ind)
+            hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, true>), dim3(grid), dim3(block), lds, st, descs, items,
+                               nitems, nrhs);
+        else
+            hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, false>), dim3(grid), dim3(block), lds, st, descs, items,
+                               nitems, nrhs);
+        return hipGetLastError();
     });
 }
 
-int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj) {
+int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj, bool ind, bool vec) {
     int blocks = 1;
     const int block = s.waves * kWave;
-    const size_t lds = size_t(s.waves) * kBatchLds;
-    const hipError_t e = by_dtype(store, [&](auto vt) -> hipError_t {
+    const hipError_t e = by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
-        return by_lanes(nrhs == 1 ? s.lanes_per_row : pow2_at_least(nrhs), [&](auto lc) -> hipError_t {
-            constexpr int LL = decltype(lc)::value;
-            if (adj) return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, 1, false>,
-                                                                         block, lds);
-            return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, 1>, block, lds);
-        });
+        constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
+        if (adj) {
+            const size_t lds = size_t(s.waves) * kBatchLds;
+            return ind ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, VX, true>,
+                                                                      block, lds)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, VX, false>,
+                                                                      block, lds);
+        }
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, VX>, block,
+                                                            size_t(s.waves) * batch_forward_lds<VT>(nrhs));
     });
     return (e != hipSuccess || blocks < 1) ? 1 : blocks;
 }

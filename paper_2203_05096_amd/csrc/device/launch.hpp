@@ -94,7 +94,7 @@ hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals,
 hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st);
 hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtype store, hipStream_t st);
 
-// Batched persistent launches over `nitems` (matrix, super-super-row) items.
+// Batched launches: one grid over `nitems` (matrix, super-super-row) items.
 // `vec`: every right-hand-side block pointer is 16-byte aligned.
 hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
                          Shape s, int grid, bool vec, hipStream_t st);
@@ -104,7 +104,7 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
                          Shape s, int grid, bool ind, bool vec, hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
-int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint);
+int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec);
 
 // Conjugate-gradient vector kernels (device/cg.hip).  FP64 vectors; q (the
 // product's output) is FP32 when q_f32.  part holds kCgGrid partial sums; s

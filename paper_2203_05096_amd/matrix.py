@@ -199,7 +199,7 @@ class CsrkSpMV(torch.autograd.Function):
 
 
 class CsrkBatch:
-    """Many CSR-k matrices (same storage type) multiplied in one persistent launch."""
+    """Many CSR-k matrices (same storage type) multiplied in one launch."""
 
     def __init__(self, mats):
         self.mats = list(mats)

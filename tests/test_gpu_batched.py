@@ -1,4 +1,4 @@
-"""GPU parity of the batched persistent launches (many matrices, blocks of right-hand sides)."""
+"""GPU parity of the batched launches (many matrices, blocks of right-hand sides)."""
 
 import concurrent.futures as cf
 
