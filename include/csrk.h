@@ -297,7 +297,11 @@ csrk_status csrk_destroy(csrk_handle h);
  * an n_b x nrhs block, in one launch over a work list of
  * (matrix, super-super-row) items.  All handles must be on the device with
  * the same storage type; they must outlive the batch.  The batch owns the
- * work list and a device pointer table.
+ * work list and one device pointer table per direction, rewritten on the
+ * call's stream when the pointers change: calls on one batch from different
+ * streams (or host threads) must be ordered by the caller, or the table can
+ * change under a launch still reading it.  The work list is cut into one
+ * contiguous range per workgroup, with 16 workgroups per CU or more.
  */
 csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_batch *out);
 

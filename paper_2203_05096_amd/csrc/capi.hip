@@ -408,9 +408,11 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
             h->split_adj = h->trans.symmetric ? h->split_fwd : xcd_split(h, h->row_ptr, &h->trans.t_row_ptr);
             // A symmetric matrix (pattern and values) is its own transpose: the
             // adjoint then reads the values the forward reads, instead of a copy.
+            // (compared bit for bit: a -0.0 mirrored by a +0.0 keeps the copy)
             h->values_symmetric = h->trans.symmetric;
             for (int64_t k = 0; h->values_symmetric && k < h->nnz; ++k)
-                h->values_symmetric = h->vals[size_t(k)] == h->vals[size_t(h->trans.t_src[size_t(k)])];
+                h->values_symmetric = std::memcmp(&h->vals[size_t(k)], &h->vals[size_t(h->trans.t_src[size_t(k)])],
+                                                  sizeof(double)) == 0;
             hip_check(hipMalloc(&h->d_vals, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals");
             if (h->values_symmetric)
                 h->d_vals_t = h->d_vals;

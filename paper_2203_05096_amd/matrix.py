@@ -82,8 +82,8 @@ class CsrkMatrix:
         return t
 
     def _check_vec(self, t, name, nrhs=None):
-        if t.device.type != "cuda" or t.dtype != self.vec_dtype or not t.is_contiguous():
-            raise TypeError(f"{name} must be a contiguous {self.vec_dtype} CUDA tensor")
+        if t.device.type != "cuda" or t.dtype != self.vec_dtype or not t.is_contiguous() or t.dim() not in (1, 2):
+            raise TypeError(f"{name} must be a contiguous {self.vec_dtype} CUDA tensor of shape (n,) or (n, nrhs)")
         if t.shape[0] != self.n:
             raise ValueError(f"{name} has {t.shape[0]} rows, matrix has {self.n}")
         k = 1 if t.dim() == 1 else t.shape[1]
@@ -98,6 +98,12 @@ class CsrkMatrix:
                 vals.numel() != self.nnz:
             raise TypeError(f"vals must be a contiguous {self.val_dtype} CUDA tensor of {self.nnz} elements")
         return vals.data_ptr()
+
+    def _check_grad_vals(self, t):
+        dt = _GRADV_DTYPE[self.store]
+        if t.dtype != dt or t.device.type != "cuda" or not t.is_contiguous() or t.numel() != self.nnz:
+            raise TypeError(f"grad_vals output must be a contiguous {dt} CUDA tensor of {self.nnz} elements")
+        return t
 
     # ---------------------------------------------------------------- products
     def spmv(self, x: torch.Tensor, y: torch.Tensor | None = None, vals: torch.Tensor | None = None) -> torch.Tensor:
@@ -142,23 +148,28 @@ class CsrkMatrix:
             gx = out_x if out_x is not None else torch.empty_like(g)
             self._check_vec(gx, "grad_x", nrhs)
         if grad_vals:
-            gv = out_vals if out_vals is not None else torch.empty(self.nnz, dtype=_GRADV_DTYPE[self.store],
-                                                                   device="cuda")
+            gv = self._check_grad_vals(out_vals) if out_vals is not None else \
+                torch.empty(self.nnz, dtype=_GRADV_DTYPE[self.store], device="cuda")
         C.csrk_spmv_adjoint(self.handle, self._check_vals(vals), _ptr(x) if grad_vals else None, _ptr(g), _ptr(gx),
                             _ptr(gv), nrhs, _stream())
         return gx, gv
 
-    def to_permuted(self, v: torch.Tensor) -> torch.Tensor:
-        nrhs = 1 if v.dim() == 1 else v.shape[1]
+    def _permute(self, v: torch.Tensor, direction: int) -> torch.Tensor:
+        if v.device.type != "cuda" or v.dim() not in (1, 2) or v.shape[0] != self.n or v.element_size() not in (4, 8):
+            raise TypeError(f"expected a CUDA tensor of shape ({self.n},) or ({self.n}, k) with 4- or 8-byte elements")
+        v = v.contiguous()
         out = torch.empty_like(v)
-        C.csrk_permute(self.handle, 0, _ptr(v.contiguous()), _ptr(out), nrhs, v.element_size(), _stream())
+        C.csrk_permute(self.handle, direction, _ptr(v), _ptr(out), 1 if v.dim() == 1 else v.shape[1],
+                       v.element_size(), _stream())
         return out
 
+    def to_permuted(self, v: torch.Tensor) -> torch.Tensor:
+        """v' = v[perm] (input order to the matrix's row order)."""
+        return self._permute(v, 0)
+
     def from_permuted(self, v: torch.Tensor) -> torch.Tensor:
-        nrhs = 1 if v.dim() == 1 else v.shape[1]
-        out = torch.empty_like(v)
-        C.csrk_permute(self.handle, 1, _ptr(v.contiguous()), _ptr(out), nrhs, v.element_size(), _stream())
-        return out
+        """v[perm] = v' (the matrix's row order back to input order)."""
+        return self._permute(v, 1)
 
     def close(self):
         if self.handle:
@@ -206,7 +217,13 @@ class CsrkBatch:
         self.store = self.mats[0].store
         self.handle = C.csrk_batch_create([m.handle for m in self.mats])
 
+    def _same_count(self, **lists):
+        for name, v in lists.items():
+            if v is not None and len(v) != len(self.mats):
+                raise ValueError(f"{name} has {len(v)} entries, the batch has {len(self.mats)} matrices")
+
     def spmv(self, xs, ys=None, vals=None):
+        self._same_count(xs=xs, ys=ys, vals=vals)
         nrhs = 1 if xs[0].dim() == 1 else xs[0].shape[1]
         if ys is None:
             ys = [torch.empty_like(x) for x in xs]
@@ -218,6 +235,7 @@ class CsrkBatch:
         return ys
 
     def adjoint(self, xs, gs, vals=None, grad_x=True, grad_vals=True, out_x=None, out_vals=None):
+        self._same_count(xs=xs if grad_vals else None, gs=gs, vals=vals, out_x=out_x, out_vals=out_vals)
         nrhs = 1 if gs[0].dim() == 1 else gs[0].shape[1]
         gxs = None
         gvs = None
@@ -226,12 +244,16 @@ class CsrkBatch:
         if grad_vals:
             gvs = out_vals if out_vals is not None else [
                 torch.empty(m.nnz, dtype=_GRADV_DTYPE[m.store], device="cuda") for m in self.mats]
-        for m, x, g in zip(self.mats, xs, gs):
-            m._check_vec(g, "g", nrhs)
+        for i, m in enumerate(self.mats):
+            m._check_vec(gs[i], "g", nrhs)
             if grad_vals:
-                m._check_vec(x, "x", nrhs)
+                m._check_vec(xs[i], "x", nrhs)
+                m._check_grad_vals(gvs[i])
+            if grad_x:
+                m._check_vec(gxs[i], "grad_x", nrhs)
         vp = None if vals is None else [m._check_vals(v) for m, v in zip(self.mats, vals)]
-        C.csrk_batch_spmv_adjoint(self.handle, vp, [_ptr(x) for x in xs], [_ptr(g) for g in gs],
+        C.csrk_batch_spmv_adjoint(self.handle, vp, [_ptr(x) for x in xs] if grad_vals else None,
+                                  [_ptr(g) for g in gs],
                                   None if gxs is None else [_ptr(t) for t in gxs],
                                   None if gvs is None else [_ptr(t) for t in gvs], nrhs, _stream())
         return gxs, gvs

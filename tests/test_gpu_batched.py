@@ -82,6 +82,32 @@ def test_batch_adjoint(small_batch):
         assert np.all(np.abs(gv.double().cpu().numpy() - refv) <= OP.gamma(8, 2.0 ** -24) * scalev)
 
 
+def test_batch_argument_checks_before_launch(small_batch):
+    """Mismatched lists and wrongly sized outputs are rejected in Python, before any pointer reaches the library."""
+    w, Ms = small_batch
+    xs, gs = _permuted(Ms, w["xs"]), _permuted(Ms, w["gs"])
+    B = CsrkBatch(Ms)
+    with pytest.raises(ValueError):
+        B.spmv(xs[:-1])  # one right-hand-side block short
+    with pytest.raises(ValueError):
+        B.adjoint(xs, gs[:-1])
+    short = [torch.empty(M.nnz - 1, device="cuda") for M in Ms]
+    with pytest.raises(TypeError):
+        B.adjoint(xs, gs, out_vals=short)
+    with pytest.raises(ValueError):
+        B.adjoint(xs, gs, out_x=[torch.empty_like(g)[:-1] for g in gs])
+    M = Ms[0]
+    with pytest.raises(TypeError):
+        M.adjoint(xs[0], gs[0], out_vals=short[0])
+    with pytest.raises(TypeError):
+        M.to_permuted(torch.zeros(M.n - 1, device="cuda"))
+    with pytest.raises(TypeError):
+        M.spmv(xs[0].reshape(M.n, 2, 4).contiguous())
+    gx, _ = B.adjoint(None, gs, grad_vals=False)  # x is not needed without grad_vals
+    torch.cuda.synchronize()
+    assert torch.equal(gx[0], M.adjoint(xs[0], gs[0], grad_vals=False)[0])
+
+
 def test_c5_full_batch_ones_closed_form_and_sampled_parity():
     w = workload_c5()
     say("c5 full build", len(w["As"]))
