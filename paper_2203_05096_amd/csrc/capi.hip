@@ -41,6 +41,7 @@ struct csrk_matrix {
     int32_t *d_long = nullptr, *d_t_long = nullptr;
     csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
     bool values_symmetric = false;  // A' == A'^T exactly: d_vals_t aliases d_vals
+    int32_t max_row_any = 0;        // longest row of A' or of A'^T
 };
 
 struct csrk_batch_s {
@@ -149,6 +150,13 @@ void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx,
     for (size_t t = 0; t + 1 < h->ssr_ptr.size(); ++t)
         h->max_ssr_rows = std::max(h->max_ssr_rows, h->sr_ptr[h->ssr_ptr[t + 1]] - h->sr_ptr[h->ssr_ptr[t]]);
     h->trans = csrk::transpose_index(h->n, h->row_ptr, h->col_idx);
+    h->max_row_any = 0;
+    for (int32_t i = 0; i < h->n; ++i) {
+        h->max_row_any = std::max(h->max_row_any, h->row_ptr[size_t(i) + 1] - h->row_ptr[size_t(i)]);
+        if (!h->trans.symmetric)
+            h->max_row_any =
+                std::max(h->max_row_any, h->trans.t_row_ptr[size_t(i) + 1] - h->trans.t_row_ptr[size_t(i)]);
+    }
 }
 
 csrk_params resolve_params(int32_t n, int64_t nnz, const csrk_params *p) {
@@ -189,6 +197,7 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.t_nlong = static_cast<int32_t>(sym ? h->long_rows.size() : h->t_long_rows.size());
     a.split_fwd = h->split_fwd;
     a.split_adj = h->split_adj;
+    a.max_row = h->max_row_any;
     return a;
 }
 

@@ -343,7 +343,50 @@ __device__ __forceinline__ typename Store<VT>::A range_adjoint(int64_t k0, int64
 // all its 16-byte loads of col_idx / values for the whole window before the
 // dependent x gathers; the row ends of the next window are fetched meanwhile;
 // products go to LDS and each row is then summed by L lanes.
-template <typename VT, int L, bool IND>
+// Row sums of a staged window: row rr (0 <= rr < nrows) owns the products
+// buf[end(rr-1) .. end(rr)), window offsets, where end(rr) = my_end of lane rr
+// minus cs; emit(rr, sum) is called by one lane per row.  Rows are reduced by
+// L lanes each, the launch shape's choice for the matrix's average row.  With
+// ADAPT (matrices with rows much longer than that shape expects), a window
+// that holds few rows gives each row more lanes, up to the whole wavefront,
+// so that a row of hundreds of products is not summed by L lanes while the
+// rest of the wavefront idles.
+template <int L, bool ADAPT, typename A, typename F>
+__device__ __forceinline__ void window_row_sums(const A *__restrict__ buf, int nrows, int32_t my_end, int32_t cs,
+                                                int lane, F &&emit) {
+    int lw = L;
+    if constexpr (ADAPT)
+        while (lw < kWave && nrows * lw * 2 <= kWave) lw *= 2;  // wavefront-uniform
+    if (!ADAPT || lw == L) {
+#pragma unroll 1
+        for (int b = 0; b < nrows; b += kWave / L) {
+            const int rr = b + lane / L;
+            const bool act = rr < nrows;
+            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+            const int32_t rbeg = rr == 0 ? 0 : prev;
+            A acc = 0;
+            if (act)
+                for (int32_t k = rbeg + (lane % L); k < rend; k += L) acc += buf[k];
+            acc = group_sum<L>(acc);
+            if (act && (lane % L) == 0) emit(rr, acc);
+        }
+        return;
+    }
+    // lw * nrows <= kWave: one pass, lw lanes per row
+    const int rr = lane / lw;
+    const bool act = rr < nrows;
+    const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+    const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+    const int32_t rbeg = rr == 0 ? 0 : prev;
+    A acc = 0;
+    if (act)
+        for (int32_t k = rbeg + (lane % lw); k < rend; k += lw) acc += buf[k];
+    for (int off = lw / 2; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+    if (act && (lane % lw) == 0) emit(rr, acc);
+}
+
+template <typename VT, int L, bool IND, bool ADAPT = false>
 __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                            const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
                                            const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
@@ -411,19 +454,7 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
 #pragma unroll
             for (int e = 0; e < V; ++e) buf[off0 + u * kWave * V + e] = v[u][e] * xv[u][e];
         wave_lds_sync();
-#pragma unroll 1
-        for (int b = 0; b < nrows; b += kWave / L) {
-            const int rr = b + lane / L;
-            const bool act = rr < nrows;
-            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
-            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
-            const int32_t rbeg = rr == 0 ? 0 : prev;
-            A acc = 0;
-            if (act)
-                for (int32_t k = rbeg + (lane % L); k < rend; k += L) acc += buf[k];
-            acc = group_sum<L>(acc);
-            if (act && (lane % L) == 0) y[ra + rr] = X(acc);
-        }
+        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { y[ra + rr] = X(acc); });
         wave_lds_sync();
         cs = ce;
         ra = nra;
@@ -508,7 +539,7 @@ __device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__
     if (threadIdx.x == 0) gx[r] = typename Store<VT>::X(t);
 }
 
-template <typename VT, int L>
+template <typename VT, int L, bool ADAPT>
 __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
@@ -530,8 +561,8 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     if (t < 0) return;
     const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward<VT, L, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x, y, nnz,
-                                 buf, lane, true);
+        sr_forward<VT, L, false, ADAPT>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x,
+                                        y, nnz, buf, lane, true);
 }
 
 // LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
@@ -1003,7 +1034,7 @@ __device__ __forceinline__ void sr_grad_vals_mrhs(int32_t r0, int32_t r1, const 
 // stored transposed copy) or vals[src[k]] (IND: values passed by the caller).
 // LDS per wavefront: products (kStageBytes) | row map (CAP bytes) | g of the
 // window's rows (64 entries).
-template <typename VT, int L, bool IND>
+template <typename VT, int L, bool IND, bool ADAPT = false>
 __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                                  const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
                                                  const VT *__restrict__ valsT,
@@ -1114,19 +1145,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
             }
         }
         wave_lds_sync();
-#pragma unroll 1
-        for (int b = 0; b < nrows; b += kWave / L) {
-            const int rr = b + lane / L;
-            const bool act = rr < nrows;
-            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
-            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
-            const int32_t rbeg = rr == 0 ? 0 : prev;
-            A acc = 0;
-            if (act)
-                for (int32_t k = rbeg + (lane % L); k < rend; k += L) acc += buf[k];
-            acc = group_sum<L>(acc);
-            if (act && (lane % L) == 0) gx[ra + rr] = X(acc);
-        }
+        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { gx[ra + rr] = X(acc); });
         wave_lds_sync();
         cs = ce;
         ra = nra;
@@ -1377,7 +1396,7 @@ constexpr int kAdjointLds = kStageBytes + kStageEntries + 64 * 8;
 // LDS bytes per wavefront of the batched kernels (any direction, any nrhs).
 constexpr int kBatchLds = kMrhsLds > kAdjointLds ? kMrhsLds : kAdjointLds;
 
-template <typename VT, int L, bool IND, bool FUSED>
+template <typename VT, int L, bool IND, bool FUSED, bool ADAPT>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
                                                        const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ cols,
@@ -1411,12 +1430,13 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
     for (int32_t s = s0 + wave; s < s1; s += nw) {
         const int32_t r0 = uniform(sr_ptr[s]), r1 = uniform(sr_ptr[s + 1]);
         if constexpr (FUSED) {
-            sr_adjoint_fused<VT, L, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane, true);
+            sr_adjoint_fused<VT, L, IND, ADAPT>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
+                                                true);
         } else {
             if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
             if (gx)
-                sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
-                                       reinterpret_cast<A *>(lds) + kStagePad, lane, true);
+                sr_forward<VT, L, IND, ADAPT>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
+                                              reinterpret_cast<A *>(lds) + kStagePad, lane, true);
         }
     }
 }
@@ -1664,6 +1684,24 @@ hipError_t by_vx(int vx, F &&f) {
 // Lanes per row for a multi-right-hand-side kernel with VX columns per lane.
 int rhs_lanes(int nrhs, int vx) { return pow2_at_least((nrhs + vx - 1) / vx); }
 
+// Whether windows of few rows get more lanes per row (window_row_sums): only
+// for matrices with rows far longer than L lanes per row is meant for, so that
+// regular matrices run the plain reduction.
+bool adapt_windows(const Arrays &a, int L) { return a.max_row > 16 * L; }
+
+// Calls f(std::bool_constant<ADAPT>); the adaptive reduction is instantiated
+// for up to 4 lanes per row (wider groups already suit long rows).
+template <int L, typename F>
+void by_adapt(bool adapt, F &&f) {
+    if constexpr (L <= 4) {
+        if (adapt) {
+            f(std::true_type{});
+            return;
+        }
+    }
+    f(std::false_type{});
+}
+
 int grid_for(int64_t work, int block) {
     int64_t g = (work + block - 1) / block;
     if (g < 1) g = 1;
@@ -1684,10 +1722,13 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
             return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
                 constexpr int L = decltype(lc)::value;
                 const int32_t long_blocks = (a.nlong + kXcds - 1) / kXcds * kXcds;
-                hipLaunchKernelGGL((k_spmv_csrk<VT, L>), dim3(long_blocks + a.split_fwd.width * kXcds), dim3(block),
-                                   size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
-                                   static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
-                                   a.nnz, a.long_rows, a.nlong, long_blocks, a.split_fwd);
+                by_adapt<L>(adapt_windows(a, L), [&](auto ac) {
+                    hipLaunchKernelGGL((k_spmv_csrk<VT, L, decltype(ac)::value>),
+                                       dim3(long_blocks + a.split_fwd.width * kXcds), dim3(block),
+                                       size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                       static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
+                                       a.nnz, a.long_rows, a.nlong, long_blocks, a.split_fwd);
+                });
                 return hipGetLastError();
             });
         }
@@ -1757,13 +1798,15 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                     const int32_t long_blocks = (na + nt + kXcds - 1) / kXcds * kXcds;
                     auto go = [&](auto fc) {
                         constexpr bool F = decltype(fc)::value;
-                        hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F>),
-                                           dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
-                                           size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
-                                           a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
-                                           static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv),
-                                           a.nnz, int(a.sym), a.long_rows, na, a.t_long_rows, nt, long_blocks,
-                                           a.split_adj);
+                        by_adapt<LL>(adapt_windows(a, LL), [&](auto ac) {
+                            hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F, decltype(ac)::value>),
+                                               dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
+                                               size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                               a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
+                                               static_cast<const X *>(x), static_cast<const X *>(g),
+                                               static_cast<X *>(gx), static_cast<A *>(gv), a.nnz, int(a.sym),
+                                               a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj);
+                        });
                     };
                     if (fused)
                         go(std::true_type{});

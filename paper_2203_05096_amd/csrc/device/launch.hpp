@@ -54,6 +54,7 @@ struct Arrays {
     int32_t t_nlong = 0;
     XcdSplit split_fwd;  // by the forward's work (rows of A')
     XcdSplit split_adj;  // by the adjoint's work (rows of A' and of A'^T)
+    int32_t max_row = 0;  // longest row of A' or of A'^T (nonzeros)
 };
 
 // Per-matrix record of a batched launch (device-resident table).

@@ -21,11 +21,11 @@ LONG_ROW = 1024  # rows longer than this get a workgroup of their own
 
 
 def _mixed(seed, symmetric, n=6000):
-    """Short rows (0..8 entries) mixed with rows of 509..520, 1023..1026, 3000 and 5000 entries, and a column
-    (7) present in every third row, so that A^T has a row of n / 3 entries too."""
+    """Short rows (0..8 entries) mixed with rows of 40..200 (windows of a few rows), 509..520, 1023..1026, 3000
+    and 5000 entries, and a column (7) present in every third row, so that A^T has a row of n / 3 entries too."""
     rng = np.random.default_rng(seed)
     special = {17: 509, 18: 510, 19: 511, 20: 520, 300: 1023, 301: 1024, 302: 1025, 303: 1026, 900: 3000,
-               2500: min(5000, n - 1), 4000 % n: 700}
+               2500: min(5000, n - 1), 4000 % n: 700, 30: 40, 31: 60, 32: 100, 33: 200, 34: 150, 35: 90, 36: 33}
     ii, jj = [], []
     for i in range(n):
         k = special.get(i, int(rng.integers(0, 9)))
@@ -70,6 +70,7 @@ def test_mixed_matrix_has_every_row_class():
     assert (lengths == LONG_ROW).any() and (lengths > LONG_ROW).sum() >= 4
     assert ((lengths > LONG_ROW) & (lengths <= 4096)).any() and (lengths > 4096).any()  # both long-row classes
     assert np.bincount(A.col_idx, minlength=A.n).max() > 1024  # and a long row of A^T
+    assert ((lengths >= 33) & (lengths <= 201)).sum() >= 7  # windows of a few rows: more lanes per row
 
 
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
