@@ -576,7 +576,9 @@ csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rt
         double *p = static_cast<double *>(buf.get(size_t(n) * 8, "cg p"));
         void *q = buf.get(size_t(n) * (lo ? 4 : 8), "cg q");
         float *p_lo = lo ? static_cast<float *>(buf.get(size_t(n) * 4, "cg p (fp32)")) : nullptr;
-        double *part = static_cast<double *>(buf.get(csrk::dev::kCgGrid * 8, "cg partial sums"));
+        // partial sums: kCgGrid for the vector kernels, one per workgroup of the product
+        const int nparts = std::max(csrk::dev::kCgGrid, csrk::dev::spmv_grid(a));
+        double *part = static_cast<double *>(buf.get(size_t(nparts) * 8, "cg partial sums"));
         double *s = static_cast<double *>(buf.get(8 * 8, "cg scalars"));
         auto spmv = [&](const void *in) {
             hip_check(csrk::dev::spmv(a, h->store, h->d_vals, in, q, 1, shp, st), "cg product");
@@ -597,11 +599,17 @@ csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rt
         const double target = rtol * (bnorm > 0 ? bnorm : 1.0);
         int32_t it = 0;
         bool done = std::sqrt(host_s[0]) <= target;
+        // Per iteration: q = A p with p . q summed per workgroup of the product
+        // (no separate pass over p and q), alpha; r -= alpha q with r . r, beta;
+        // then x += alpha p and p = r + beta p in one pass over p.
         while (!done && it < max_iter) {
-            spmv(lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(p));
-            hip_check(csrk::dev::cg_alpha(p, q, lo, n, part, s, st), "cg alpha");
-            hip_check(csrk::dev::cg_step(x_dev, r, p, q, lo, n, part, s, st), "cg step");
-            hip_check(csrk::dev::cg_set_p(r, p, p_lo, s, n, true, st), "cg p");
+            hip_check(csrk::dev::spmv_dot(a, h->store, h->d_vals,
+                                          lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(p), q, p,
+                                          part, shp, st),
+                      "cg product");
+            hip_check(csrk::dev::cg_alpha_parts(part, csrk::dev::spmv_grid(a), s, st), "cg alpha");
+            hip_check(csrk::dev::cg_update_r(r, q, lo, n, part, s, st), "cg residual update");
+            hip_check(csrk::dev::cg_update_xp(x_dev, p, p_lo, r, s, n, st), "cg x and p update");
             ++it;
             if (it % check_every == 0 || it == max_iter) {
                 read_scalars();

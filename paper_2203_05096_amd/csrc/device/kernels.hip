@@ -386,12 +386,15 @@ __device__ __forceinline__ void window_row_sums(const A *__restrict__ buf, int n
     if (act && (lane % lw) == 0) emit(rr, acc);
 }
 
-template <typename VT, int L, bool IND, bool ADAPT = false>
+// With DOT, the lane that stores y[i] also adds y[i] * pdot[i] (FP64, y as
+// stored) to *dot: the product's inner product with a vector, for CG.
+template <typename VT, int L, bool IND, bool ADAPT = false, bool DOT = false>
 __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                            const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
                                            const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                            typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                           typename Store<VT>::A *__restrict__ buf, int lane, bool skip_long) {
+                                           typename Store<VT>::A *__restrict__ buf, int lane, bool skip_long,
+                                           const double *__restrict__ pdot = nullptr, double *dot = nullptr) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
@@ -413,7 +416,10 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
             const int32_t re = uniform(__shfl(my_end, 0));
             if (!(skip_long && re - cs > kLongRow)) {
                 const A acc = range_dot<VT, IND>(cs, re, cols, src, vals, x, nnz, lane);
-                if (lane == 0) y[ra] = X(acc);
+                if (lane == 0) {
+                    y[ra] = X(acc);
+                    if constexpr (DOT) *dot += double(X(acc)) * pdot[ra];
+                }
             }
             cs = re;
             ++ra;
@@ -454,7 +460,10 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
 #pragma unroll
             for (int e = 0; e < V; ++e) buf[off0 + u * kWave * V + e] = v[u][e] * xv[u][e];
         wave_lds_sync();
-        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { y[ra + rr] = X(acc); });
+        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) {
+            y[ra + rr] = X(acc);
+            if constexpr (DOT) *dot += double(X(acc)) * pdot[ra + rr];
+        });
         wave_lds_sync();
         cs = ce;
         ra = nra;
@@ -489,19 +498,25 @@ __device__ __forceinline__ A block_total(A sum, unsigned char *smem, int wave, i
     return t;
 }
 
-// y[r] for long row r by the whole workgroup.
+// y[r] for long row r by the whole workgroup (with pdot: thread 0 adds
+// y[r] * pdot[r] to *dot).
 template <typename VT>
 __device__ __forceinline__ void long_row_forward(int32_t r, const int32_t *__restrict__ row_ptr,
                                                  const int32_t *__restrict__ cols, const VT *__restrict__ vals,
                                                  const typename Store<VT>::X *__restrict__ x,
                                                  typename Store<VT>::X *__restrict__ y, int64_t nnz,
-                                                 unsigned char *smem, int wave, int nw, int lane) {
+                                                 unsigned char *smem, int wave, int nw, int lane,
+                                                 const double *__restrict__ pdot = nullptr, double *dot = nullptr) {
     using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
     int64_t a, b;
     long_slice<Store<VT>::V>(row_ptr[r], row_ptr[r + 1], wave, nw, a, b);
     const A sum = (a < b) ? range_dot<VT, false>(a, b, cols, nullptr, vals, x, nnz, lane) : A(0);
     const A t = block_total(sum, smem, wave, nw, lane);
-    if (threadIdx.x == 0) y[r] = typename Store<VT>::X(t);
+    if (threadIdx.x == 0) {
+        y[r] = X(t);
+        if (pdot) *dot += double(X(t)) * pdot[r];
+    }
 }
 
 // Long-row item `item` of the adjoint: items [0, na) are long rows of A'
@@ -563,6 +578,53 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     for (int32_t s = s0 + wave; s < s1; s += nw)
         sr_forward<VT, L, false, ADAPT>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x,
                                         y, nnz, buf, lane, true);
+}
+
+// The forward product y = A'x plus, per workgroup, the partial inner product
+// sum_i y_i pdot_i (FP64, y as stored), written to part[blockIdx.x] by every
+// workgroup (0 where it has no rows).  Each lane accumulates the rows it
+// stores, in storage order; lanes, then wavefronts, are added in a fixed
+// order, so the partials do not depend on timing.  Used by CG for p . Ap.
+template <typename VT, int L>
+__global__ void __launch_bounds__(1024) k_spmv_csrk_dot(const int32_t *__restrict__ ssr_ptr,
+                                                        const int32_t *__restrict__ sr_ptr,
+                                                        const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ cols, const VT *__restrict__ vals,
+                                                        const typename Store<VT>::X *__restrict__ x,
+                                                        typename Store<VT>::X *__restrict__ y, int64_t nnz,
+                                                        const int32_t *__restrict__ long_rows, int32_t nlong,
+                                                        int32_t long_blocks, XcdSplit split,
+                                                        const double *__restrict__ pdot, double *__restrict__ part) {
+    using A = typename Store<VT>::A;
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ double wsum[1024 / kWave];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
+    const int32_t bid = int32_t(blockIdx.x);
+    double dot = 0;
+    if (bid < long_blocks) {
+        if (bid < nlong)
+            long_row_forward<VT>(long_rows[bid], row_ptr, cols, vals, x, y, nnz, smem, wave, nw, lane, pdot, &dot);
+    } else {
+        A *buf = reinterpret_cast<A *>(smem + size_t(wave) * kStageBytes) + kStagePad;
+        const int32_t t = ssr_of_block(split, bid - long_blocks);
+        if (t >= 0) {
+            const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
+            for (int32_t s = s0 + wave; s < s1; s += nw)
+                sr_forward<VT, L, false, false, true>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols,
+                                                      nullptr, vals, x, y, nnz, buf, lane, true, pdot, &dot);
+        }
+    }
+#pragma unroll
+    for (int off = kWave / 2; off >= 1; off >>= 1) dot += __shfl_xor(dot, off);
+    if (lane == 0) wsum[wave] = dot;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0;
+        for (int w = 0; w < nw; ++w) t += wsum[w];
+        part[bid] = t;
+    }
 }
 
 // LDS bytes per wavefront of the multi-right-hand-side kernels: a window of
@@ -1743,6 +1805,29 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
                                    a.nnz, nrhs, a.split_fwd);
                 return hipGetLastError();
             });
+        });
+    });
+}
+
+int spmv_grid(const Arrays &a) {
+    return (a.nlong + kXcds - 1) / kXcds * kXcds + a.split_fwd.width * kXcds;
+}
+
+hipError_t spmv_dot(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, const double *pdot,
+                    double *part, Shape s, hipStream_t st) {
+    if (a.nssr == 0) return hipSuccess;
+    const int block = s.waves * kWave;
+    return by_dtype(store, [&](auto vt) -> hipError_t {
+        using VT = decltype(vt);
+        using X = typename Store<VT>::X;
+        return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
+            constexpr int L = decltype(lc)::value;
+            const int32_t long_blocks = (a.nlong + kXcds - 1) / kXcds * kXcds;
+            hipLaunchKernelGGL((k_spmv_csrk_dot<VT, L>), dim3(spmv_grid(a)), dim3(block),
+                               size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                               static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y), a.nnz,
+                               a.long_rows, a.nlong, long_blocks, a.split_fwd, pdot, part);
+            return hipGetLastError();
         });
     });
 }

@@ -84,6 +84,12 @@ struct Shape {
     int waves = 4;
 };
 
+// y = A'x (one right-hand side) and part[w] = the partial sum of y_i pdot_i
+// over workgroup w's rows, for w < spmv_grid(a) (CG's p . Ap; FP64).
+int spmv_grid(const Arrays &a);
+hipError_t spmv_dot(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, const double *pdot,
+                    double *part, Shape s, hipStream_t st);
+
 hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, int nrhs, Shape s,
                 hipStream_t st);
 hipError_t spmv_plain(const Arrays &a, csrk_dtype store, const void *vals, const void *x, void *y, int nrhs,
@@ -108,8 +114,9 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec);
 
 // Conjugate-gradient vector kernels (device/cg.hip).  FP64 vectors; q (the
-// product's output) is FP32 when q_f32.  part holds kCgGrid partial sums; s
-// the scalars rr, pq, alpha, beta, rr_new, bb at s[0..5].
+// product's output) is FP32 when q_f32.  part holds kCgGrid partial sums
+// (or spmv_grid's, for cg_alpha_parts); s the scalars rr, pq, alpha, beta,
+// rr_new, bb at s[0..5].
 constexpr int kCgGrid = 1024;
 int cg_grid(int64_t n);
 // r = b - q, s[0] = r . r
@@ -120,11 +127,13 @@ hipError_t cg_norm2(const double *b, int64_t n, double *part, double *s, hipStre
 // p = r + beta p (p = r when !use_beta); p_lo = float(p) when p_lo != NULL
 hipError_t cg_set_p(const double *r, double *p, float *p_lo, const double *s, int64_t n, bool use_beta,
                     hipStream_t st);
-// s[1] = p . q, s[2] = alpha = s[0] / s[1]
-hipError_t cg_alpha(const double *p, const void *q, bool q_f32, int64_t n, double *part, double *s, hipStream_t st);
-// x += alpha p, r -= alpha q, s[4] = r . r, s[3] = beta = s[4] / s[0], s[0] = s[4]
-hipError_t cg_step(double *x, double *r, const double *p, const void *q, bool q_f32, int64_t n, double *part,
-                   double *s, hipStream_t st);
+// s[1] = sum of part[0..count) (p . q from spmv_dot), s[2] = alpha = s[0] / s[1]
+hipError_t cg_alpha_parts(const double *part, int count, double *s, hipStream_t st);
+// r -= alpha q, s[4] = r . r, s[3] = beta = s[4] / s[0], s[0] = s[4]
+hipError_t cg_update_r(double *r, const void *q, bool q_f32, int64_t n, double *part, double *s, hipStream_t st);
+// x += alpha p, then p = r + beta p (one pass over the old p); p_lo = float(p) when p_lo != NULL
+hipError_t cg_update_xp(double *x, double *p, float *p_lo, const double *r, const double *s, int64_t n,
+                        hipStream_t st);
 // out = float(v)
 hipError_t cg_round(const double *v, float *out, int64_t n, hipStream_t st);
 
