@@ -259,8 +259,10 @@ csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nt
  * when ||r||_2 <= rtol * ||b||_2 (r the recurrence residual, checked every
  * check_every iterations) or after max_iter iterations; *iters_out and
  * *rel_resid_out (both may be NULL) receive the iteration count and
- * ||r||_2 / ||b||_2.  Allocates 4 work vectors on the device for the call and
- * synchronises `stream` before returning.  Errors: CSRK_ERR_ARG (null
+ * ||r||_2 / ||b||_2.  Allocates, for the call, 3 work vectors on the device
+ * (4 with FP32/BF16 storage) and one FP64 partial sum per workgroup of the
+ * product (p'Ap is summed by the product's own workgroups), and synchronises
+ * `stream` before returning.  Errors: CSRK_ERR_ARG (null
  * vectors, rtol <= 0, max_iter < 0, check_every < 1), CSRK_ERR_UNSUPPORTED on
  * a breakdown (p'A p <= 0: the stored matrix is not positive definite),
  * CSRK_ERR_ALLOC, CSRK_ERR_DEVICE.
