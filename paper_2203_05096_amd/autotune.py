@@ -139,8 +139,10 @@ def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes
              "waves_per_wg": min(ssrs, 16) if waves_list is None else waves_list[0], "reorder": reorder}
         return sizes, C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
 
+    combos = list(itertools.product(srs_list, ssrs_list))
     with cf.ThreadPoolExecutor(threads) as ex:
-        for (srs, ssrs), h in ex.map(build, itertools.product(srs_list, ssrs_list)):
+        # `threads` host builds at a time, so at most that many structures are held at once
+        for (srs, ssrs), h in (r for i in range(0, len(combos), threads) for r in ex.map(build, combos[i:i + threads])):
             C.csrk_upload(h, store)
             M = CsrkMatrix(h, store)
             for lanes, waves in itertools.product(lanes_list, [min(ssrs, 16)] if waves_list is None else waves_list):
@@ -255,6 +257,49 @@ def markdown(groups: dict, consts: dict, command: str) -> str:
     return "\n".join(lines)
 
 
+def time_params(A, p: dict, store: str = "f64", reps: int = 40, objective: str = "forward") -> float:
+    """Event time (microseconds) of one parameter set on matrix A: the forward, or forward + adjoint."""
+    dt = torch.float64 if store == "f64" else torch.float32
+    n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
+    M = CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = torch.rand(n, generator=g, device="cuda", dtype=dt) * 2 - 1
+    y = torch.empty_like(x)
+    if objective == "forward":
+        us = time_forward(M, x, y, reps)
+    else:
+        gv = torch.empty(nnz, device="cuda", dtype=dt)
+        us = time_step(M, x, torch.rand(n, generator=g, device="cuda", dtype=dt), y, torch.empty_like(x), gv, reps)
+    M.close()
+    return us
+
+
+def grid_markdown(res: SweepResult, picks: dict, command: str) -> str:
+    """The (SRS x SSRS) grid of one matrix (best over lanes per cell), its optimum, and each model's pick timed
+    on the same matrix."""
+    srs_l = sorted({t.srs for t in res.trials})
+    ssrs_l = sorted({t.ssrs for t in res.trials})
+    b = res.best
+    lines = [f"Matrix {res.name}: n = {res.n:,}, nnz = {res.nnz:,}, rdensity {res.rdensity:.3f}.", "",
+             "Command:", "", "    " + command, "",
+             "Forward kernel time in us per (SRS, SSRS) cell, the best over lanes per row; waves per workgroup = "
+             "min(SSRS, 16):", "",
+             "| SRS \\ SSRS | " + " | ".join(str(v) for v in ssrs_l) + " |",
+             "|---|" + "---|" * len(ssrs_l)]
+    for srs in srs_l:
+        cells = []
+        for ssrs in ssrs_l:
+            t = res.best_for(srs, ssrs)
+            cells.append(f"{t.us:.1f}" if t else "")
+        lines.append(f"| {srs} | " + " | ".join(cells) + " |")
+    lines += ["", f"Optimum: SRS {b.srs}, SSRS {b.ssrs}, lanes {b.lanes}, waves {b.waves}: {b.us:.1f} us.", "",
+              "| model | (SRS, SSRS, lanes, waves) | us | model / optimum |", "|---|---|---|---|"]
+    for name, (p, us) in picks.items():
+        lines.append(f"| {name} | ({p['srs']}, {p['ssrs']}, {p['lanes_per_row']}, {p['waves_per_wg']}) | {us:.1f} | "
+                     f"{us / b.us:.3f} |")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     import os
     ap = argparse.ArgumentParser(description=__doc__)
@@ -265,8 +310,33 @@ def main(argv=None):
     ap.add_argument("--objective", choices=["forward", "step"], default="step")
     ap.add_argument("--from-json", nargs="+", default=None,
                     help="fit and evaluate earlier --out reports together instead of sweeping")
-    ap.add_argument("--markdown", default=None, help="with --from-json: write a summary table here")
+    ap.add_argument("--markdown", default=None, help="with --from-json or --workload: write a summary table here")
+    ap.add_argument("--workload", default=None, help="sweep one named workload of gen (e.g. c2) instead of the suite")
+    ap.add_argument("--srs", default=None, help="comma-separated SRS values (with --workload)")
+    ap.add_argument("--ssrs", default=None, help="comma-separated SSRS values (with --workload)")
+    ap.add_argument("--lanes", default="1,2,4", help="comma-separated lanes per row (with --workload)")
     args = ap.parse_args(argv)
+    if args.workload:
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import gen
+        A = gen.WORKLOADS[args.workload]()["A"]
+        ints = lambda v, d: tuple(int(t) for t in v.split(",")) if v else d  # noqa: E731
+        res = sweep(A, args.store, srs_list=ints(args.srs, SRS_SWEEP), ssrs_list=ints(args.ssrs, SSRS_SWEEP),
+                    lanes_list=ints(args.lanes, LANES_SWEEP), threads=args.threads, objective=args.objective,
+                    name=args.workload)
+        n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
+        picks = {}
+        for model in ("mi355x", "volta", "ampere"):
+            p = C.csrk_tune(n, nnz, model)
+            p["waves_per_wg"] = min(p["waves_per_wg"], 16)
+            picks[model] = (p, time_params(A, p, args.store, objective=args.objective))
+        cmd = "python -m paper_2203_05096_amd.autotune " + " ".join(argv if argv is not None else sys.argv[1:])
+        text = grid_markdown(res, picks, cmd)
+        print(text, flush=True)
+        if args.markdown:
+            with open(args.markdown, "w") as f:
+                f.write(text)
+        return
     if args.from_json:
         groups = {}
         for p in args.from_json:

@@ -60,3 +60,15 @@ def test_fit_and_model_pick_over_two_matrices():
         assert e["model_srs"] in (16, 32, 64) and e["model_ssrs"] in (2, 4)
         assert e["ratio"] >= 1.0
         assert e["best"]["us"] == res.best.us
+
+
+def test_workload_grid_report(tmp_path, capsys):
+    """The single-workload grid sweep: every cell timed, the optimum and the three models' picks reported."""
+    out = tmp_path / "grid.md"
+    say("autotune grid c1")
+    T.main(["--workload", "c1", "--store", "f64", "--objective", "forward", "--srs", "8,16", "--ssrs", "2,4",
+            "--lanes", "1,2", "--threads", "2", "--markdown", str(out)])
+    text = out.read_text()
+    assert "| 8 | " in text and "| 16 | " in text and "Optimum: SRS" in text
+    for model in ("mi355x", "volta", "ampere"):
+        assert f"| {model} | (" in text
