@@ -2,7 +2,7 @@
 
 The paper's test suite has an irregular class (row-length variance above 10:
 web, citation, social and circuit graphs, Table 1) on which CSR-3 loses most,
-because long rows end up summed serially (Section 5.5).  These matrices are
+because long rows end up summed serially (Section 7, GPU performance).  These matrices are
 not available here; R-MAT graphs stand in for them: recursive quadrant
 sampling with probabilities (a, b, c, d) gives a heavy-tailed degree
 distribution with a few very long rows and many short ones.

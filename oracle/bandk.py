@@ -31,14 +31,12 @@ deterministic reading of those gaps (listed in the project design notes):
     order1 = Expand(G1, order2) is the SR order; perm = Expand(G0, order1).
 7.  sr_ptr / ssr_ptr are running counts of rows per SR and SRs per SSR
     (Section 2.2 and Fig. 1).
-8.  Irregular matrices (this library's extension; the paper leaves load
-    balance on irregular matrices as future work, Section 5.5): an SR whose
-    cost, the sum of its rows' lengths with rows longer than LONG_ROW counted
-    as 0, exceeds B = max(2048, ceil(4 * SRS * nnz / n)) is cut greedily into
-    consecutive pieces of cost at most B (a row is added to the current piece
-    unless the piece is non-empty and the row would take it above B); every
-    piece is an SR, and the pieces of each SSR are regrouped SSRS at a time.
-    A grouping with no SR above B is left as it is.
+
+The library may refine this grouping further for its own kernels (cutting
+super-rows of heavy irregular matrices into pieces); that refinement is not
+part of the paper's method and is not modelled here: the tests check it on the
+library's own output by invariants, and compare bit for bit wherever it leaves
+the grouping unchanged.
 
 The ordering's *quality* is parity unpinned: no implementation of the paper's
 Band-k exists to compare against; only this reading is pinned (worked example,
@@ -302,53 +300,14 @@ def bandwidth(row_ptr, col_idx) -> int:
     return int(np.max(np.abs(rows - np.asarray(col_idx, dtype=np.int64))))
 
 
-LONG_ROW = 1024  # rows longer than this are computed outside their super-row
-
-
-def sr_budget(n: int, nnz: int, srs: int) -> int:
-    """B = max(2048, ceil(4 * SRS * nnz / n)), in integers."""
-    return 2048 if n <= 0 else max(2048, -(-(4 * srs * nnz) // n))
-
-
-def balance(perm, sr_ptr, ssr_ptr, row_ptr, srs: int, ssrs: int):
-    """Step 8 above: returns the new (sr_ptr, ssr_ptr); perm is unchanged.  row_ptr is the input matrix's."""
-    row_ptr = np.asarray(row_ptr, dtype=np.int64)
-    n, nnz = len(row_ptr) - 1, int(row_ptr[-1])
-    budget = sr_budget(n, nnz, srs)
-    lengths = np.diff(row_ptr)[np.asarray(perm, dtype=np.int64)]
-    cost = [0 if int(L) > LONG_ROW else int(L) for L in lengths]
-    sr_sizes, ssr_sizes, split = [], [], False
-    for t in range(len(ssr_ptr) - 1):
-        pieces = []
-        for s in range(int(ssr_ptr[t]), int(ssr_ptr[t + 1])):
-            a, b = int(sr_ptr[s]), int(sr_ptr[s + 1])
-            if sum(cost[a:b]) <= budget:
-                pieces.append(b - a)
-                continue
-            split = True
-            start, acc = a, 0
-            for i in range(a, b):
-                if i > start and acc + cost[i] > budget:
-                    pieces.append(i - start)
-                    start, acc = i, 0
-                acc += cost[i]
-            pieces.append(b - start)
-        sr_sizes.extend(pieces)
-        ssr_sizes.extend(min(ssrs, len(pieces) - q) for q in range(0, len(pieces), ssrs))
-    if not split:
-        return np.asarray(sr_ptr, dtype=np.int64), np.asarray(ssr_ptr, dtype=np.int64)
-    return running_counts(sr_sizes), running_counts(ssr_sizes)
-
-
 def build_grouping(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk", k: int = 3):
-    """Ordering + grouping as the library's host build forms it: the reordering's grouping (Band-k with k
-    levels, RCM with fixed chunks, or the input order with fixed chunks), then step 8."""
+    """Ordering + grouping of steps 1-7: Band-k with k levels, RCM with fixed chunks, or the input order with
+    fixed chunks."""
     if reorder == "bandk":
         perm, sr_ptr, ssr_ptr = (bandk_v1 if k == 3 else bandk_k2)(row_ptr, col_idx, srs, ssrs)
     elif reorder == "rcm":
         perm, sr_ptr, ssr_ptr = reorder_rcm(row_ptr, col_idx, srs, ssrs)
     else:
         perm, sr_ptr, ssr_ptr = reorder_none(len(row_ptr) - 1, srs, ssrs)
-    sr_ptr, ssr_ptr = balance(perm, sr_ptr, ssr_ptr, row_ptr, srs, ssrs)
     return perm, sr_ptr, ssr_ptr
 

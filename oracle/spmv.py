@@ -80,11 +80,3 @@ def row_abs_sum(row_ptr, col_idx, vals, x) -> np.ndarray:
     """sum_j |a_ij| |x_j| per row (the scale of the forward error bound), FP64."""
     return spmv(row_ptr, col_idx, np.abs(np.asarray(vals, dtype=np.float64)), np.abs(np.asarray(x, dtype=np.float64)))
 
-
-def to_dense(n, row_ptr, col_idx, vals) -> np.ndarray:
-    """Dense FP64 copy of a CSR matrix (small n only)."""
-    D = np.zeros((n, n), dtype=np.float64)
-    for i in range(n):
-        for k in range(int(row_ptr[i]), int(row_ptr[i + 1])):
-            D[i, int(col_idx[k])] += float(vals[k])
-    return D

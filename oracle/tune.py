@@ -87,11 +87,6 @@ def paper_tune(n: int, nnz: int, model: str, srss_reading: str = "ssrs"):
     return max(1, ssrs), max(1, srs), c
 
 
-def block_dims(r: float):
-    """The paper's thread-block shape per case (x, y[, z]); context only."""
-    return {1: (8, 12), 2: (4, 8, 12), 3: (8, 8, 8), 4: (16, 8, 4)}[case_of(r)]
-
-
 def sweep_set_gpu():
     """The paper's GPU sweep values {2^i, 1.5 * 2^i}, i = 2..5."""
     return sorted({2 ** i for i in range(2, 6)} | {3 * 2 ** (i - 1) for i in range(2, 6)})

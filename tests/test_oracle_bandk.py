@@ -168,73 +168,6 @@ def test_band_close_to_rcm_on_grid():
     assert B.bandwidth(r3, c3) <= B.bandwidth(r2, c2) <= 4 * B.bandwidth(r3, c3)
 
 
-# ---------------------------------------------------------------- step 8: super-row budget (irregular matrices)
-
-def _lengths_matrix(lengths, n):
-    """Row i holds lengths[i] distinct columns (row i itself first, then 0, 1, 2, ... skipping i)."""
-    rows, cols = [], []
-    for i, L in enumerate(lengths):
-        c = [i] + [j for j in range(L + 1) if j != i][:L - 1] if L else []
-        rows += [i] * len(c)
-        cols += sorted(c)
-    rp = np.zeros(n + 1, np.int64)
-    np.cumsum(np.bincount(np.asarray(rows, np.int64), minlength=n), out=rp[1:])
-    return rp.astype(np.int32), np.asarray(cols, np.int32)
-
-
-def test_balance_worked_example():
-    # SRS 8, SSRS 2, input order.  Rows 0..7 have 1000, 1000, 1000, 100, 1000, 3000, 1, 1 nonzeros; the other
-    # 3992 rows one each: nnz = 11094, B = max(2048, ceil(4 * 8 * 11094 / 4000)) = 2048.  SR 0 costs
-    # 4102 (the 3000-entry row is long and costs 0): greedy pieces {0,1} (2000), {2,3} (1100; row 4 would give
-    # 2100), {4..7} (1002).  SSR 0 = SR 0 + SR 1 becomes 4 pieces, regrouped two at a time.
-    n = 4000
-    rp, ci = _lengths_matrix([1000, 1000, 1000, 100, 1000, 3000, 1, 1] + [1] * (n - 8), n)
-    assert int(rp[-1]) == 11094 and B.sr_budget(n, 11094, 8) == 2048
-    perm, sr_ptr, ssr_ptr = B.build_grouping(rp, ci, 8, 2, "none")
-    assert np.array_equal(perm, np.arange(n))
-    assert np.array_equal(sr_ptr, B.running_counts([2, 2, 4, 8] + [8] * 498))
-    assert np.array_equal(ssr_ptr, B.running_counts([2, 2] + [2] * 249))
-
-
-def test_balance_leaves_regular_groupings_alone():
-    A = workload_c1()["A"]
-    for reorder in ("bandk", "rcm", "none"):
-        p0 = {"bandk": lambda: B.bandk_v1(A.row_ptr, A.col_idx, 64, 8),
-              "rcm": lambda: B.reorder_rcm(A.row_ptr, A.col_idx, 64, 8),
-              "none": lambda: B.reorder_none(A.n, 64, 8)}[reorder]()
-        p1 = B.build_grouping(A.row_ptr, A.col_idx, 64, 8, reorder)
-        assert all(np.array_equal(a, b) for a, b in zip(p0, p1))
-
-
-@pytest.mark.parametrize("reorder", ["bandk", "none"])
-def test_balance_invariants_rmat(reorder):
-    from gen.irregular import rmat_matrix
-    A = rmat_matrix(12, 6.0, 9, symmetric=True)
-    srs, ssrs = 64, 4
-    perm0, sr0, ssr0 = B.bandk_v1(A.row_ptr, A.col_idx, srs, ssrs) if reorder == "bandk" else \
-        B.reorder_none(A.n, srs, ssrs)
-    perm, sr, ssr = B.build_grouping(A.row_ptr, A.col_idx, srs, ssrs, reorder)
-    assert np.array_equal(perm, perm0)
-    budget = B.sr_budget(A.n, A.nnz, srs)
-    L = np.diff(A.row_ptr.astype(np.int64))[perm]
-    cost = np.where(L > B.LONG_ROW, 0, L)
-    c = np.concatenate([[0], np.cumsum(cost)])
-    sr_cost = c[sr[1:]] - c[sr[:-1]]
-    assert len(sr) > len(sr0)  # something was split
-    assert np.all((sr_cost <= budget) | (np.diff(sr) == 1))
-    assert np.all(np.diff(sr) >= 1) and np.all(np.diff(sr) <= srs)
-    assert set(sr0.tolist()) <= set(sr.tolist())  # pieces only cut existing super-rows
-    # every original SSR start is still an SSR start (in rows), and SSRs hold at most SSRS super-rows
-    assert set(sr0[ssr0].tolist()) <= set(sr[ssr].tolist())
-    assert np.all(np.diff(ssr) >= 1) and np.all(np.diff(ssr) <= ssrs)
-    # greedy: a piece plus the next row of the same original super-row would exceed the budget
-    ends = set(sr0.tolist())
-    for s in range(len(sr) - 1):
-        b = int(sr[s + 1])
-        if b not in ends:
-            assert sr_cost[s] + cost[b] > budget
-
-
 # ---------------------------------------------------------------- CSR-2 (k = 2)
 
 def test_csr2_worked_example_path12():
