@@ -40,7 +40,8 @@ extern "C" {
 typedef enum csrk_status {
     CSRK_OK = 0,
     CSRK_ERR_ARG = 1,          /* bad argument: null pointer, size <= 0 where forbidden, bad enum, misaligned pointer */
-    CSRK_ERR_NOT_SQUARE = 2,   /* reserved: the API only takes square matrices (n rows, columns < n) */
+    /* 2 is not used: a matrix is given by its n rows and columns in [0, n), so a
+       non-square input shows up as CSRK_ERR_COL_RANGE */
     CSRK_ERR_BAD_ROWPTR = 3,   /* row_ptr[0] != 0, decreasing, or row_ptr[n] != nnz */
     CSRK_ERR_COL_RANGE = 4,    /* a column index outside [0, n) */
     CSRK_ERR_DUPLICATE = 5,    /* the same column twice in one row */
@@ -57,9 +58,16 @@ typedef enum csrk_status {
 
 typedef enum csrk_dtype { CSRK_F64 = 0, CSRK_F32 = 1, CSRK_BF16 = 2 } csrk_dtype;
 
-/* Size models.  VOLTA and AMPERE are the paper's fitted formulas (Section 4.1);
- * MI355X is this library's fit of the same form for gfx950. */
-typedef enum csrk_model { CSRK_MODEL_MI355X = 0, CSRK_MODEL_VOLTA = 1, CSRK_MODEL_AMPERE = 2 } csrk_model;
+/* Size models.  VOLTA and AMPERE are the paper's fitted GPU formulas (Section
+ * 4.1); MI355X is this library's fit of the same form for gfx950; HOST_CPU is
+ * the paper's constant-time CPU choice (Section 4.2): CSR-2 with SRS = 96 for
+ * every matrix, the fallback when the matrix is not tuned individually. */
+typedef enum csrk_model {
+    CSRK_MODEL_MI355X = 0,
+    CSRK_MODEL_VOLTA = 1,
+    CSRK_MODEL_AMPERE = 2,
+    CSRK_MODEL_HOST_CPU = 3
+} csrk_model;
 
 /* Row orderings: Band-k (Section 2.2; this library's deterministic reading),
  * reverse Cuthill-McKee of the symmetrised pattern, or the input order. */
@@ -98,7 +106,7 @@ typedef struct csrk_info {
     int32_t on_device;        /* 1 when device arrays exist */
     int32_t store;            /* csrk_dtype of the device values (valid when on_device) */
     int32_t long_rows;        /* rows with more than CSRK_LONG_ROW nonzeros: each is computed
-                                 by a workgroup of its own (Section 5.5 names computing
+                                 by a workgroup of its own (Section 7 names computing
                                  dense rows in parallel as the fix for irregular matrices) */
     int32_t values_symmetric; /* 1 when uploaded and A' equals A'^T exactly: the adjoint then
                                  reads the forward's values instead of a transposed copy */
@@ -119,7 +127,9 @@ const char *csrk_last_error_detail(void);
  * alone (rdensity = nnz / n; Section 4.1).  VOLTA/AMPERE reproduce the
  * paper's formulas: round-half-up logarithmic fits and the per-case
  * adjustments, "SRSS" read as SSRS, results clamped to >= 1.  MI355X uses
- * this library's constants of the same form.  O(1), no allocation.
+ * this library's constants of the same form.  HOST_CPU gives k = 2,
+ * srs = 96, ssrs = 1 (each super-row is one unit of the host kernel's
+ * parallel loop; Section 4.2) for any n and nnz.  O(1), no allocation.
  * Errors: CSRK_ERR_ARG for n <= 0, nnz <= 0, unknown model or out == NULL.
  */
 csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out);
@@ -140,8 +150,12 @@ csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model
  * csrk_build_host — validate the CSR input, build the symmetrised graph,
  * reorder (Band-k / RCM / none), apply the symmetric permutation (columns
  * sorted within rows) and form sr_ptr / ssr_ptr (Section 2.2).  Host only: no
- * HIP call.  row_ptr[n+1], col_idx[nnz] and vals[nnz] (FP64, may be NULL for
- * a pattern-only build, values then 0) are borrowed for the call and copied.
+ * HIP call.  row_ptr[n+1], col_idx[nnz] and vals[nnz] are borrowed for the
+ * call and copied.  vals holds nnz values of in_dtype (F64: double, F32:
+ * float, BF16: the 16-bit patterns as uint16_t), or is NULL for a
+ * pattern-only build (values then 0).  The host keeps the values in FP64;
+ * FP32 and BF16 inputs widen exactly, so a later upload in the input's own
+ * type reproduces them bit for bit.
  * Columns may be unsorted within a row; duplicates are rejected.  p == NULL
  * uses csrk_tune(n, nnz, CSRK_MODEL_MI355X).  The result is deterministic:
  * the same input gives a bit-identical structure.
@@ -152,12 +166,12 @@ csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model
  * super-super-row are regrouped SSRS at a time.  A regular matrix (no
  * super-row above B) keeps the plain grouping.  This is this library's
  * extension: the paper leaves load balance on irregular matrices as future
- * work (Section 5.5).
- * Errors: CSRK_ERR_ARG, CSRK_ERR_BAD_ROWPTR, CSRK_ERR_COL_RANGE,
- * CSRK_ERR_DUPLICATE, CSRK_ERR_ALLOC.
+ * work (Section 7).
+ * Errors: CSRK_ERR_ARG (also for an unknown in_dtype), CSRK_ERR_BAD_ROWPTR,
+ * CSRK_ERR_COL_RANGE, CSRK_ERR_DUPLICATE, CSRK_ERR_ALLOC.
  */
 csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
-                            const double *vals, const csrk_params *p, csrk_handle *out);
+                            const void *vals, csrk_dtype in_dtype, const csrk_params *p, csrk_handle *out);
 
 /*
  * csrk_build_from_groups — like csrk_build_host but with a caller-given
@@ -167,8 +181,9 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
  * such as those of Fig. 1 are expressed.
  */
 csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
-                                   const double *vals, const int32_t *perm, int32_t nsr, const int32_t *sr_sizes,
-                                   int32_t nssr, const int32_t *ssr_sizes, const csrk_params *p, csrk_handle *out);
+                                   const void *vals, csrk_dtype in_dtype, const int32_t *perm, int32_t nsr,
+                                   const int32_t *sr_sizes, int32_t nssr, const int32_t *ssr_sizes,
+                                   const csrk_params *p, csrk_handle *out);
 
 /*
  * csrk_upload — copy a host-built handle's arrays to the current HIP device
@@ -179,9 +194,10 @@ csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_pt
  */
 csrk_status csrk_upload(csrk_handle h, csrk_dtype store);
 
-/* csrk_build = csrk_build_host followed by csrk_upload. */
-csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
-                       const csrk_params *p, csrk_dtype store, csrk_handle *out);
+/* csrk_build = csrk_build_host followed by csrk_upload(store).  On failure
+ * *out is NULL and nothing is left allocated. */
+csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const void *vals,
+                       csrk_dtype in_dtype, csrk_dtype store, const csrk_params *p, csrk_handle *out);
 
 /*
  * csrk_set_launch — change the kernel launch shape of a built handle
@@ -215,6 +231,16 @@ csrk_status csrk_copy_structure(csrk_handle h, int32_t *perm, int32_t *row_ptr, 
  * calls through their vals_dev argument instead.
  */
 csrk_status csrk_device_vals(csrk_handle h, void **vals_dev);
+
+/*
+ * csrk_copy_device_vals — enqueue on `stream` a device-to-device copy of the
+ * handle's stored values (nnz entries of the storage type, CSR-k order) into
+ * the caller's buffer dst_dev (at least nnz * element size bytes, caller
+ * owned).  Asynchronous like the products.  Errors: CSRK_ERR_ARG (null
+ * handle or destination), CSRK_ERR_UNSUPPORTED (host-only handle),
+ * CSRK_ERR_DEVICE.
+ */
+csrk_status csrk_copy_device_vals(csrk_handle h, void *dst_dev, void *stream);
 
 /*
  * csrk_spmv — y' = A' x' (Section 1 statement of SpMV on the CSR-k arrays;
@@ -317,6 +343,20 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
                                     void *const *grad_x, void *const *grad_vals, int32_t nrhs, void *stream);
 
 csrk_status csrk_batch_destroy(csrk_batch b);
+
+/*
+ * Bandwidth probes (measurement aids, not part of the product): the HBM rate
+ * attainable on the device, against which the products' achieved rates are
+ * read (Section 1 explains why SpMV is bound by memory bandwidth).
+ * csrk_probe_read streams `bytes` of device memory (a multiple of 16, buf_dev
+ * 16-byte aligned) with 16-byte non-temporal loads and writes 4096 doubles of
+ * checksum to part_dev (caller owned); csrk_probe_copy copies `bytes` from
+ * src_dev to dst_dev (both 16-byte aligned, not overlapping) with 16-byte
+ * non-temporal loads and stores.  Asynchronous on `stream`.  Errors:
+ * CSRK_ERR_ARG, CSRK_ERR_DEVICE.
+ */
+csrk_status csrk_probe_read(const void *buf_dev, int64_t bytes, double *part_dev, void *stream);
+csrk_status csrk_probe_copy(const void *src_dev, void *dst_dev, int64_t bytes, void *stream);
 
 #ifdef __cplusplus
 }

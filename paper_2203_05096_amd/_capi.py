@@ -19,10 +19,10 @@ HEADER = os.path.join(os.path.dirname(PKG), "include", "csrk.h")
 
 F64, F32, BF16 = 0, 1, 2
 DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
-MODELS = {"mi355x": 0, "volta": 1, "ampere": 2}
+MODELS = {"mi355x": 0, "volta": 1, "ampere": 2, "host_cpu": 3}
 REORDERS = {"bandk": 0, "rcm": 1, "none": 2}
-STATUS = ["CSRK_OK", "CSRK_ERR_ARG", "CSRK_ERR_NOT_SQUARE", "CSRK_ERR_BAD_ROWPTR", "CSRK_ERR_COL_RANGE",
-          "CSRK_ERR_DUPLICATE", "CSRK_ERR_ALLOC", "CSRK_ERR_DEVICE", "CSRK_ERR_UNSUPPORTED"]
+STATUS = {0: "CSRK_OK", 1: "CSRK_ERR_ARG", 3: "CSRK_ERR_BAD_ROWPTR", 4: "CSRK_ERR_COL_RANGE",
+          5: "CSRK_ERR_DUPLICATE", 6: "CSRK_ERR_ALLOC", 7: "CSRK_ERR_DEVICE", 8: "CSRK_ERR_UNSUPPORTED"}
 
 
 class csrk_params(ctypes.Structure):
@@ -50,7 +50,7 @@ class csrk_info(ctypes.Structure):
 class CsrkError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         self.status = status
-        self.name = STATUS[status] if 0 <= status < len(STATUS) else str(status)
+        self.name = STATUS.get(status, str(status))
         super().__init__(f"{where}: {self.name}: {detail}")
 
 
@@ -69,17 +69,19 @@ _SIGS = {
     "csrk_spmv_host": ([_h, _f64p, _f64p, ctypes.c_int32], ctypes.c_int),
     "csrk_cg": ([_h, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
-    "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params),
-                         ctypes.POINTER(_h)], ctypes.c_int),
-    "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, _i32p, ctypes.c_int32, _i32p,
-                                ctypes.c_int32, _i32p, ctypes.POINTER(csrk_params), ctypes.POINTER(_h)], ctypes.c_int),
+    "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _vp, ctypes.c_int,
+                         ctypes.POINTER(csrk_params), ctypes.POINTER(_h)], ctypes.c_int),
+    "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _vp, ctypes.c_int, _i32p, ctypes.c_int32,
+                                _i32p, ctypes.c_int32, _i32p, ctypes.POINTER(csrk_params), ctypes.POINTER(_h)],
+                               ctypes.c_int),
     "csrk_upload": ([_h, ctypes.c_int], ctypes.c_int),
-    "csrk_build": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _f64p, ctypes.POINTER(csrk_params), ctypes.c_int,
-                    ctypes.POINTER(_h)], ctypes.c_int),
+    "csrk_build": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _vp, ctypes.c_int, ctypes.c_int,
+                    ctypes.POINTER(csrk_params), ctypes.POINTER(_h)], ctypes.c_int),
     "csrk_set_launch": ([_h, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "csrk_get_info": ([_h, ctypes.POINTER(csrk_info)], ctypes.c_int),
     "csrk_copy_structure": ([_h, _i32p, _i32p, _i32p, _f64p, _i64p, _i32p, _i32p], ctypes.c_int),
     "csrk_device_vals": ([_h, ctypes.POINTER(_vp)], ctypes.c_int),
+    "csrk_copy_device_vals": ([_h, _vp, _vp], ctypes.c_int),
     "csrk_spmv": ([_h, _vp, _vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "csrk_spmv_plain": ([_h, _vp, _vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
     "csrk_spmv_adjoint": ([_h, _vp, _vp, _vp, _vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -91,6 +93,8 @@ _SIGS = {
     "csrk_batch_spmv_adjoint": ([_h, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32, _vp], ctypes.c_int),
     "csrk_batch_destroy": ([_h], ctypes.c_int),
+    "csrk_probe_read": ([_vp, ctypes.c_int64, _vp, _vp], ctypes.c_int),
+    "csrk_probe_copy": ([_vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
 }
 
 _lib = None
@@ -136,6 +140,23 @@ def _f64(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
 
 
+_IN_DTYPE = {np.dtype(np.float64): F64, np.dtype(np.float32): F32, np.dtype(np.uint16): BF16}
+
+
+def _vals(a, in_dtype=None):
+    """(contiguous value array, csrk_dtype): float64 -> F64, float32 -> F32, uint16 (BF16 bit patterns) -> BF16;
+    other types are converted to float64.  ``in_dtype`` ("f64", "f32", "bf16") forces the type."""
+    if a is None:
+        return None, F64
+    if in_dtype is not None:
+        dt = {"f64": np.float64, "f32": np.float32, "bf16": np.uint16}[in_dtype]
+        return np.ascontiguousarray(a, dtype=dt), DTYPES[in_dtype]
+    a = np.asarray(a)
+    if a.dtype in _IN_DTYPE:
+        return np.ascontiguousarray(a), _IN_DTYPE[a.dtype]
+    return np.ascontiguousarray(a, dtype=np.float64), F64
+
+
 def _params(p):
     if p is None:
         return None
@@ -175,22 +196,28 @@ def csrk_tune_rhs(n: int, nnz: int, nrhs: int, model: str = "mi355x") -> dict:
     return p.as_dict()
 
 
-def csrk_build_host(row_ptr, col_idx, vals=None, params=None) -> int:
-    rp, ci, va = _i32(row_ptr), _i32(col_idx), _f64(vals)
+def _vptr(a):
+    return None if a is None else a.ctypes.data
+
+
+def csrk_build_host(row_ptr, col_idx, vals=None, params=None, in_dtype=None) -> int:
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    va, vt = _vals(vals, in_dtype)
     h = _h()
     p = _params(params)
     _check(lib().csrk_build_host(len(rp) - 1, int(rp[-1]) if len(rp) else 0, _ptr(rp, _i32p), _ptr(ci, _i32p),
-                                 _ptr(va, _f64p), ctypes.byref(p) if p is not None else None, ctypes.byref(h)),
+                                 _vptr(va), vt, ctypes.byref(p) if p is not None else None, ctypes.byref(h)),
            "csrk_build_host")
     return h.value
 
 
-def csrk_build_from_groups(row_ptr, col_idx, vals, perm, sr_sizes, ssr_sizes, params=None) -> int:
-    rp, ci, va = _i32(row_ptr), _i32(col_idx), _f64(vals)
+def csrk_build_from_groups(row_ptr, col_idx, vals, perm, sr_sizes, ssr_sizes, params=None, in_dtype=None) -> int:
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    va, vt = _vals(vals, in_dtype)
     pm, srz, ssrz = _i32(perm), _i32(sr_sizes), _i32(ssr_sizes)
     h = _h()
     p = _params(params)
-    _check(lib().csrk_build_from_groups(len(rp) - 1, int(rp[-1]), _ptr(rp, _i32p), _ptr(ci, _i32p), _ptr(va, _f64p),
+    _check(lib().csrk_build_from_groups(len(rp) - 1, int(rp[-1]), _ptr(rp, _i32p), _ptr(ci, _i32p), _vptr(va), vt,
                                         _ptr(pm, _i32p), len(srz), _ptr(srz, _i32p), len(ssrz), _ptr(ssrz, _i32p),
                                         ctypes.byref(p) if p is not None else None, ctypes.byref(h)),
            "csrk_build_from_groups")
@@ -201,12 +228,14 @@ def csrk_upload(h: int, store: str = "f64"):
     _check(lib().csrk_upload(h, DTYPES[store]), "csrk_upload")
 
 
-def csrk_build(row_ptr, col_idx, vals, params=None, store: str = "f64") -> int:
-    rp, ci, va = _i32(row_ptr), _i32(col_idx), _f64(vals)
+def csrk_build(row_ptr, col_idx, vals, params=None, store: str = "f64", in_dtype=None) -> int:
+    """Host build + upload.  ``vals``: float64, float32 or uint16 (BF16 bit patterns) array, or None."""
+    rp, ci = _i32(row_ptr), _i32(col_idx)
+    va, vt = _vals(vals, in_dtype)
     h = _h()
     p = _params(params)
-    _check(lib().csrk_build(len(rp) - 1, int(rp[-1]), _ptr(rp, _i32p), _ptr(ci, _i32p), _ptr(va, _f64p),
-                            ctypes.byref(p) if p is not None else None, DTYPES[store], ctypes.byref(h)), "csrk_build")
+    _check(lib().csrk_build(len(rp) - 1, int(rp[-1]), _ptr(rp, _i32p), _ptr(ci, _i32p), _vptr(va), vt, DTYPES[store],
+                            ctypes.byref(p) if p is not None else None, ctypes.byref(h)), "csrk_build")
     return h.value
 
 
@@ -236,6 +265,10 @@ def csrk_device_vals(h: int) -> int:
     p = _vp()
     _check(lib().csrk_device_vals(h, ctypes.byref(p)), "csrk_device_vals")
     return p.value
+
+
+def csrk_copy_device_vals(h: int, dst_dev, stream):
+    _check(lib().csrk_copy_device_vals(h, dst_dev, stream), "csrk_copy_device_vals")
 
 
 def csrk_spmv(h: int, vals_dev, x_dev, y_dev, nrhs: int, stream):
@@ -304,3 +337,11 @@ def csrk_batch_spmv_adjoint(b: int, vals, x, g, grad_x, grad_vals, nrhs: int, st
 
 def csrk_batch_destroy(b: int):
     _check(lib().csrk_batch_destroy(b), "csrk_batch_destroy")
+
+
+def csrk_probe_read(buf_dev, nbytes: int, part_dev, stream):
+    _check(lib().csrk_probe_read(buf_dev, int(nbytes), part_dev, stream), "csrk_probe_read")
+
+
+def csrk_probe_copy(src_dev, dst_dev, nbytes: int, stream):
+    _check(lib().csrk_probe_copy(src_dev, dst_dev, int(nbytes), stream), "csrk_probe_copy")

@@ -159,6 +159,30 @@ void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx,
     }
 }
 
+// The host keeps an FP64 master copy of the values.  FP32 and BF16 input
+// values widen to FP64 exactly, so converting back to the input's own type at
+// upload returns the caller's bits.  Returns a pointer to FP64 values (the
+// input itself when it already is FP64; NULL for a pattern-only build).
+const double *values_as_f64(const void *vals, csrk_dtype in, int64_t nnz, std::vector<double> &buf) {
+    if (in != CSRK_F64 && in != CSRK_F32 && in != CSRK_BF16) throw Error{CSRK_ERR_ARG, "unknown input dtype"};
+    if (!vals) return nullptr;
+    if (in == CSRK_F64) return static_cast<const double *>(vals);
+    buf.resize(size_t(nnz));
+    if (in == CSRK_F32) {
+        const float *f = static_cast<const float *>(vals);
+        for (int64_t k = 0; k < nnz; ++k) buf[size_t(k)] = double(f[k]);
+    } else {
+        const uint16_t *b = static_cast<const uint16_t *>(vals);
+        for (int64_t k = 0; k < nnz; ++k) {
+            const uint32_t u = uint32_t(b[k]) << 16;
+            float f;
+            std::memcpy(&f, &u, sizeof(f));
+            buf[size_t(k)] = double(f);
+        }
+    }
+    return buf.data();
+}
+
 csrk_params resolve_params(int32_t n, int64_t nnz, const csrk_params *p) {
     csrk_params q{};
     if (p) {
@@ -278,8 +302,6 @@ const char *csrk_status_string(csrk_status s) {
         return "CSRK_OK";
     case CSRK_ERR_ARG:
         return "CSRK_ERR_ARG: invalid argument";
-    case CSRK_ERR_NOT_SQUARE:
-        return "CSRK_ERR_NOT_SQUARE: matrix is not square";
     case CSRK_ERR_BAD_ROWPTR:
         return "CSRK_ERR_BAD_ROWPTR: malformed row_ptr";
     case CSRK_ERR_COL_RANGE:
@@ -329,11 +351,13 @@ csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model
 }
 
 csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
-                            const double *vals, const csrk_params *p, csrk_handle *out) {
+                            const void *vals_in, csrk_dtype in_dtype, const csrk_params *p, csrk_handle *out) {
     return guard([&] {
         if (!out) throw Error{CSRK_ERR_ARG, "out is NULL"};
         *out = nullptr;
         csrk::validate_csr(n, nnz, row_ptr, col_idx);
+        std::vector<double> widened;
+        const double *vals = values_as_f64(vals_in, in_dtype, nnz, widened);
         csrk_params q = resolve_params(n, nnz, p);
         csrk::Grouping gr;
         if (q.reorder == CSRK_REORDER_BANDK) {
@@ -363,12 +387,15 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
 }
 
 csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
-                                   const double *vals, const int32_t *perm, int32_t nsr, const int32_t *sr_sizes,
-                                   int32_t nssr, const int32_t *ssr_sizes, const csrk_params *p, csrk_handle *out) {
+                                   const void *vals_in, csrk_dtype in_dtype, const int32_t *perm, int32_t nsr,
+                                   const int32_t *sr_sizes, int32_t nssr, const int32_t *ssr_sizes,
+                                   const csrk_params *p, csrk_handle *out) {
     return guard([&] {
         if (!out) throw Error{CSRK_ERR_ARG, "out is NULL"};
         *out = nullptr;
         csrk::validate_csr(n, nnz, row_ptr, col_idx);
+        std::vector<double> widened;
+        const double *vals = values_as_f64(vals_in, in_dtype, nnz, widened);
         if (n > 0 && !perm) throw Error{CSRK_ERR_ARG, "perm is NULL"};
         csrk_params q = resolve_params(n, nnz, p);
         csrk::Grouping gr = csrk::from_sizes(std::vector<int32_t>(perm, perm + n), sr_sizes, nsr, ssr_sizes, nssr);
@@ -447,9 +474,9 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
     });
 }
 
-csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const double *vals,
-                       const csrk_params *p, csrk_dtype store, csrk_handle *out) {
-    csrk_status s = csrk_build_host(n, nnz, row_ptr, col_idx, vals, p, out);
+csrk_status csrk_build(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx, const void *vals,
+                       csrk_dtype in_dtype, csrk_dtype store, const csrk_params *p, csrk_handle *out) {
+    csrk_status s = csrk_build_host(n, nnz, row_ptr, col_idx, vals, in_dtype, p, out);
     if (s != CSRK_OK) return s;
     s = csrk_upload(*out, store);
     if (s != CSRK_OK) {
@@ -522,6 +549,19 @@ csrk_status csrk_device_vals(csrk_handle h, void **vals_dev) {
         need_device(h);
         if (!vals_dev) throw Error{CSRK_ERR_ARG, "null output"};
         *vals_dev = h->d_vals;
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_copy_device_vals(csrk_handle h, void *dst_dev, void *stream) {
+    return guard([&] {
+        need_device(h);
+        if (!dst_dev && h->nnz > 0) throw Error{CSRK_ERR_ARG, "dst_dev is NULL"};
+        if (h->nnz == 0) return CSRK_OK;
+        DeviceScope ds(h->device);
+        hip_check(hipMemcpyAsync(dst_dev, h->d_vals, size_t(h->nnz) * dtype_bytes(h->store), hipMemcpyDeviceToDevice,
+                                 static_cast<hipStream_t>(stream)),
+                  "csrk_copy_device_vals");
         return CSRK_OK;
     });
 }
@@ -846,6 +886,27 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
                                            batch_grid(b, nrhs, true, ind, vec), ind, vec, st),
                   "csrk_batch_spmv_adjoint launch");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_probe_read(const void *buf_dev, int64_t bytes, double *part_dev, void *stream) {
+    return guard([&] {
+        if (bytes < 0 || bytes % 16 || (bytes > 0 && (!buf_dev || !part_dev)))
+            throw Error{CSRK_ERR_ARG, "need bytes >= 0, a multiple of 16, and non-null buffers"};
+        check_align16(buf_dev, "buf_dev");
+        hip_check(csrk::dev::probe_read(buf_dev, bytes, part_dev, static_cast<hipStream_t>(stream)), "csrk_probe_read");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_probe_copy(const void *src_dev, void *dst_dev, int64_t bytes, void *stream) {
+    return guard([&] {
+        if (bytes < 0 || bytes % 16 || (bytes > 0 && (!src_dev || !dst_dev)))
+            throw Error{CSRK_ERR_ARG, "need bytes >= 0, a multiple of 16, and non-null buffers"};
+        check_align16(src_dev, "src_dev");
+        check_align16(dst_dev, "dst_dev");
+        hip_check(csrk::dev::probe_copy(src_dev, dst_dev, bytes, static_cast<hipStream_t>(stream)), "csrk_probe_copy");
         return CSRK_OK;
     });
 }

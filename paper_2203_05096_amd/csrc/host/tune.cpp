@@ -69,6 +69,14 @@ int32_t clamp_size(int64_t v, int64_t hi) { return static_cast<int32_t>(std::max
 
 csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
     if (!out || n <= 0 || nnz <= 0) return CSRK_ERR_ARG;
+    if (model == CSRK_MODEL_HOST_CPU) {
+        // Section 4.2: on CPUs CSR-2 is preferred and the best SRS does not
+        // follow the matrix's simple statistics; a geometric mean of the
+        // per-matrix optima, 96, is the constant-time choice.  ssrs = 1 makes
+        // every super-row a unit of the host kernel's parallel loop.
+        *out = csrk_params{2, 96, 1, 1, 4, CSRK_REORDER_BANDK};
+        return CSRK_OK;
+    }
     const double r = double(nnz) / double(n);
     const double lr = std::log(r);
     const int c = case_of(r);

@@ -8,8 +8,6 @@ torch tensors on the GPU in the matrix's permuted row order; ``to_permuted`` /
 
 from __future__ import annotations
 
-import ctypes
-
 import numpy as np
 import torch
 
@@ -18,18 +16,6 @@ from . import _capi as C
 _VEC_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
 _VAL_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}
 _GRADV_DTYPE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.float32}
-
-_hip = None
-
-
-def _hip_memcpy_d2d(dst: int, src: int, nbytes: int):
-    global _hip
-    if _hip is None:
-        _hip = ctypes.CDLL("libamdhip64.so")
-        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
-        _hip.hipMemcpy.restype = ctypes.c_int
-    if nbytes and _hip.hipMemcpy(dst, src, nbytes, 3) != 0:  # hipMemcpyDeviceToDevice
-        raise RuntimeError("hipMemcpy failed")
 
 
 def _stream():
@@ -77,8 +63,7 @@ class CsrkMatrix:
     def values(self) -> torch.Tensor:
         """A new tensor holding the stored values (CSR-k order, storage dtype)."""
         t = torch.empty(self.nnz, dtype=self.val_dtype, device="cuda")
-        torch.cuda.current_stream().synchronize()
-        _hip_memcpy_d2d(t.data_ptr(), C.csrk_device_vals(self.handle), self.nnz * t.element_size())
+        C.csrk_copy_device_vals(self.handle, t.data_ptr(), _stream())
         return t
 
     def _check_vec(self, t, name, nrhs=None):
