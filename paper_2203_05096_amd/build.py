@@ -19,7 +19,8 @@ LIB = os.path.join(OUT_DIR, "libcsrk.so")
 BUILD_DIR = os.path.join(ROOT, "_build", "csrk")
 
 HOST_SOURCES = ["host/graph.cpp", "host/csr.cpp", "host/tune.cpp", "host/cpu_spmv.cpp"]
-HIP_SOURCES = ["device/kernels.hip", "device/cg.hip", "capi.hip"]
+HIP_SOURCES = ["device/forward.hip", "device/adjoint.hip", "device/batch.hip", "device/util.hip", "device/cg.hip",
+               "capi.hip"]
 
 ARCH = os.environ.get("CSRK_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

@@ -1,0 +1,139 @@
+// Adjoint kernels (grad_x = A'^T g, grad_vals = g_i x_j) for one and for
+// several right-hand sides, with their launcher.
+#include "common.hpp"
+
+namespace csrk {
+namespace dev {
+
+namespace {
+
+template <typename VT, int L, bool IND, bool FUSED, bool ADAPT>
+__global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
+                                                       const int32_t *__restrict__ row_ptr,
+                                                       const int32_t *__restrict__ cols,
+                                                       const int32_t *__restrict__ t_row_ptr,
+                                                       const int32_t *__restrict__ t_col,
+                                                       const int32_t *__restrict__ t_src, const VT *__restrict__ valsT,
+                                                       const typename Store<VT>::X *__restrict__ x,
+                                                       const typename Store<VT>::X *__restrict__ g,
+                                                       typename Store<VT>::X *__restrict__ gx,
+                                                       typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym,
+                                                       const int32_t *__restrict__ long_rows, int32_t na,
+                                                       const int32_t *__restrict__ t_long_rows, int32_t nt,
+                                                       int32_t long_blocks, XcdSplit split) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
+    const int32_t bid = int32_t(blockIdx.x);
+    if (bid < long_blocks) {
+        if (bid < na + nt)
+            long_row_adjoint<VT, IND, FUSED>(bid, long_rows, na, t_long_rows, row_ptr, cols, t_row_ptr, t_col,
+                                             t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw, lane);
+        return;
+    }
+    unsigned char *lds = smem + size_t(wave) * kAdjointLds;
+    const int32_t t = ssr_of_block(split, bid - long_blocks);
+    if (t < 0) return;
+    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
+    // one instantiation per path keeps the other path's registers out of it
+    using A = typename Store<VT>::A;
+    for (int32_t s = s0 + wave; s < s1; s += nw) {
+        const int32_t r0 = uniform(sr_ptr[s]), r1 = uniform(sr_ptr[s + 1]);
+        if constexpr (FUSED) {
+            sr_adjoint_fused<VT, L, IND, ADAPT>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
+                                                true);
+        } else {
+            if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
+            if (gx)
+                sr_forward<VT, L, IND, ADAPT>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
+                                              reinterpret_cast<A *>(lds) + kStagePad, lane, true);
+        }
+    }
+}
+
+template <typename VT, int RL, int VX, bool IND>
+__global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
+    const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr, const int32_t *__restrict__ row_ptr,
+    const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr, const int32_t *__restrict__ t_col,
+    const int32_t *__restrict__ t_src, const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
+    const typename Store<VT>::X *__restrict__ g, typename Store<VT>::X *__restrict__ gx,
+    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, int sym, XcdSplit split) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave = uniform(threadIdx.x / kWave);
+    const int nw = blockDim.x / kWave;
+    unsigned char *lds = smem + size_t(wave) * kMrhsLds;
+    const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
+    if (t < 0) return;
+    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
+    for (int32_t s = s0 + wave; s < s1; s += nw)
+        sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
+                                         t_src, valsT, x, g, gx, gv, nnz, nrhs, sym != 0, lds, lane);
+}
+
+}  // namespace
+
+hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const void *x, const void *g, void *gx,
+                   void *gv, int nrhs, Shape s, hipStream_t st) {
+    if (a.nssr == 0) return hipSuccess;
+    const int block = s.waves * kWave;
+    // Values passed by the caller are reached through the transposed map; the
+    // handle's own values use its stored transposed copy.
+    const bool ind = vals != nullptr;
+    return by_dtype(store, [&](auto vt) -> hipError_t {
+        using VT = decltype(vt);
+        using X = typename Store<VT>::X;
+        using A = typename Store<VT>::A;
+        const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
+        auto launch = [&](auto indc) -> hipError_t {
+            constexpr bool IND = decltype(indc)::value;
+            if (nrhs == 1) {
+                return by_lanes(s.lanes_per_row, [&](auto lc) -> hipError_t {
+                    constexpr int LL = decltype(lc)::value;
+                    // The long rows the main blocks leave out: long rows of A' for
+                    // grad_vals (and grad_x when fused), long rows of A'^T for grad_x
+                    // otherwise.
+                    const bool fused = a.sym && gx && gv;
+                    const int32_t na = (fused || gv) ? a.nlong : 0;
+                    const int32_t nt = (!fused && gx) ? a.t_nlong : 0;
+                    const int32_t long_blocks = (na + nt + kXcds - 1) / kXcds * kXcds;
+                    auto go = [&](auto fc) {
+                        constexpr bool F = decltype(fc)::value;
+                        by_adapt<LL>(adapt_windows(a, LL), [&](auto ac) {
+                            hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F, decltype(ac)::value>),
+                                               dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
+                                               size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                               a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
+                                               static_cast<const X *>(x), static_cast<const X *>(g),
+                                               static_cast<X *>(gx), static_cast<A *>(gv), a.nnz, int(a.sym),
+                                               a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj);
+                        });
+                    };
+                    if (fused)
+                        go(std::true_type{});
+                    else
+                        go(std::false_type{});
+                    return hipGetLastError();
+                });
+            }
+            const int vx = vec_cols<X>(nrhs, {x, g, gx});
+            return by_vx<X>(vx, [&](auto vc) -> hipError_t {
+                constexpr int VX = decltype(vc)::value;
+                return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
+                    constexpr int RL = decltype(rc)::value;
+                    hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.split_adj.width * kXcds),
+                                       dim3(block), size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                       a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
+                                       nrhs, int(a.sym), a.split_adj);
+                    return hipGetLastError();
+                });
+            });
+        };
+        return ind ? launch(std::true_type{}) : launch(std::false_type{});
+    });
+}
+
+}  // namespace dev
+}  // namespace csrk

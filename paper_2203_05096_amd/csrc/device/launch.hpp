@@ -1,5 +1,5 @@
-// Launchers of the gfx950 kernels (device/kernels.hip).  C++ linkage, used
-// only by the C ABI layer.
+// Launchers of the gfx950 kernels (device/forward.hip, adjoint.hip, batch.hip,
+// util.hip, cg.hip).  C++ linkage, used only by the C ABI layer.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -112,6 +112,13 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec);
+
+// Bandwidth probes (device/util.hip): a streaming read of `bytes` (a multiple of
+// 16, 16-byte aligned) writing one word per workgroup to part[0 .. probe_grid()),
+// and a copy of `bytes` from src to dst.
+int probe_grid();
+hipError_t probe_read(const void *buf, int64_t bytes, double *part, hipStream_t st);
+hipError_t probe_copy(const void *src, void *dst, int64_t bytes, hipStream_t st);
 
 // Conjugate-gradient vector kernels (device/cg.hip).  FP64 vectors; q (the
 // product's output) is FP32 when q_f32.  part holds kCgGrid partial sums
