@@ -270,3 +270,61 @@ def test_symmetric_values_share_the_forward_array():
     gx, gv = _adjoint(MZ, np.ones(Z.n), np.ones(Z.n))
     # and the adjoint through the copy agrees with the oracle
     _check_grad_x(gx, Z, np.ones(Z.n), "f64", False, "signed zeros")
+
+
+def test_c2_full_adjoint_random_vectors_at_tuned_shape():
+    """The benchmark's adjoint: the full 128^3 scrambled 7-point matrix at the tuned shape, fused path reading
+    the forward's own values, random x and g: grad_vals bitwise, grad_x within 1e-12 sum |a||g|."""
+    from gen import workload_c2
+    w = workload_c2()
+    A, x, g = w["A"], w["x"], w["g"]
+    p = C.csrk_tune(A.n, A.nnz, "mi355x")
+    say("c2 full adjoint", p)
+    M = _build(A, "f64", p)
+    assert M.info["values_symmetric"] == 1
+    gx, gv = _adjoint(M, x, g)
+    assert np.array_equal(gv, OA.grad_vals(A.row_ptr, A.col_idx, x, g))
+    _check_grad_x(gx, A, g, "f64", False, "c2 full")
+
+
+@pytest.mark.parametrize("nrhs", [3, 8])
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("symmetric", [False, True])
+@pytest.mark.parametrize("explicit_vals", [False, True])
+def test_adjoint_multi_rhs_precisions(nrhs, store, symmetric, explicit_vals):
+    """Blocks of right-hand sides in every storage type, symmetric (one fused pass when both outputs are wanted
+    and the accumulation is FP32) and nonsymmetric patterns (grad_vals, then A'^T g), with the handle's values
+    or values passed in."""
+    A = random_sparse(2500, 7.0, seed=40 + nrhs, empty_row_frac=0.05, symmetric_pattern=symmetric)
+    A.vals = OP.stored_values(A.vals, store)
+    rng = np.random.default_rng(41 + nrhs)
+    X = rng.uniform(-1, 1, (A.n, nrhs))
+    G = rng.uniform(-1, 1, (A.n, nrhs))
+    if store != "f64":
+        X, G = X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
+    say("adjoint mrhs", nrhs, store, symmetric, explicit_vals)
+    M = _build(A, store, params(21, 4))
+    s = M.structure()
+    perm, vmap = s["perm"], s["vmap"]
+    dt = VEC[store]
+    vals = M.values() if explicit_vals else None
+    gx, gv = M.adjoint(to_dev(X[perm], dt), to_dev(G[perm], dt), vals=vals)
+    torch.cuda.synchronize()
+    gx_in = np.empty((A.n, nrhs))
+    gx_in[perm] = gx.double().cpu().numpy()
+    gv_in = np.empty(A.nnz)
+    gv_in[vmap] = gv.double().cpu().numpy()
+    # values and vectors are exact in the storage type: only the accumulation rounds
+    ref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, G)
+    scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(G))
+    colcount = np.maximum(np.bincount(A.col_idx, minlength=A.n), 1)[:, None]
+    beta = np.full(colcount.shape, 1e-12) if store == "f64" else OP.gamma(colcount, 2.0 ** -24)
+    assert np.all(np.abs(gx_in - ref) <= beta * scale), f"grad_x over bound by {np.max(np.abs(gx_in - ref) - beta * scale)}"
+    refv = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    scalev = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+    betav = 1e-12 if store == "f64" else OP.gamma(nrhs, 2.0 ** -24)
+    assert np.all(np.abs(gv_in - refv) <= betav * scalev)
+    # grad_vals does not depend on the values: the same with or without them, and bitwise per column block
+    _, gv2 = M.adjoint(to_dev(X[perm], dt), to_dev(G[perm], dt), vals=vals, grad_x=False)
+    torch.cuda.synchronize()
+    assert torch.equal(gv2, gv)

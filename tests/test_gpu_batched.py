@@ -108,10 +108,16 @@ def test_batch_argument_checks_before_launch(small_batch):
     assert torch.equal(gx[0], M.adjoint(xs[0], gs[0], grad_vals=False)[0])
 
 
-def test_c5_full_batch_ones_closed_form_and_sampled_parity():
+@pytest.fixture(scope="module")
+def full_c5():
     w = workload_c5()
     say("c5 full build", len(w["As"]))
     Ms = _build_all(w["As"])
+    return w, Ms
+
+
+def test_c5_full_batch_ones_closed_form_and_sampled_parity(full_c5):
+    w, Ms = full_c5
     B = CsrkBatch(Ms)
     ones = [torch.ones((M.n, 8), dtype=torch.float32, device="cuda") for M in Ms]
     ys = B.spmv(ones)
@@ -128,3 +134,86 @@ def test_c5_full_batch_ones_closed_form_and_sampled_parity():
     for b in (0, 17, 63):
         M, A, X = Ms[b], w["As"][b], w["xs"][b]
         check_forward(ys[b].double().cpu().numpy(), A, X, M.structure()["perm"], "f32", False, label=f"c5[{b}]")
+
+
+def test_c5_full_batch_adjoint_sampled_parity(full_c5):
+    """The benchmark's batched adjoint at full size (64 matrices, 8 right-hand sides, FP32), one launch; matrices
+    0, 17 and 63 against the oracle: grad_x per column within gamma_{c_j}(2^-24), grad_vals (a sum over the 8
+    columns) within gamma_8(2^-24); every matrix's grad_vals equal to its single-matrix launch bit for bit."""
+    w, Ms = full_c5
+    B = CsrkBatch(Ms)
+    xs, gs = _permuted(Ms, w["xs"]), _permuted(Ms, w["gs"])
+    gxs, gvs = B.adjoint(xs, gs)
+    torch.cuda.synchronize()
+    for b in (0, 17, 63):
+        say("c5 adjoint matrix", b)
+        M, s = Ms[b], Ms[b].structure()
+        X, G = xs[b].double().cpu().numpy(), gs[b].double().cpu().numpy()
+        ref = OA.grad_x(s["row_ptr"], s["col_idx"], s["vals"], G)
+        scale = OA.grad_x(s["row_ptr"], s["col_idx"], np.abs(s["vals"]), np.abs(G))
+        colcount = np.maximum(np.bincount(s["col_idx"], minlength=M.n), 1)[:, None]
+        assert np.all(np.abs(gxs[b].double().cpu().numpy() - ref) <= OP.gamma(colcount, 2.0 ** -24) * scale)
+        refv = OA.grad_vals(s["row_ptr"], s["col_idx"], X, G)
+        scalev = OA.grad_vals(s["row_ptr"], s["col_idx"], np.abs(X), np.abs(G))
+        assert np.all(np.abs(gvs[b].double().cpu().numpy() - refv) <= OP.gamma(8, 2.0 ** -24) * scalev)
+        gx1, gv1 = M.adjoint(xs[b], gs[b])
+        torch.cuda.synchronize()
+        assert torch.equal(gv1, gvs[b]) and torch.equal(gx1, gxs[b])
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("nrhs", [1, 8])
+@pytest.mark.parametrize("explicit_vals", [False, True])
+def test_batch_adjoint_precisions_mixed_patterns(store, nrhs, explicit_vals):
+    """A batch mixing symmetric and nonsymmetric patterns in every storage type, one and eight right-hand sides,
+    handle values or values passed in: each matrix against the oracle at its bound and against its own
+    single-matrix launch."""
+    from gen import random_sparse
+    mats = [random_sparse(n, 6.0, seed=60 + i, empty_row_frac=0.05, symmetric_pattern=(i % 2 == 0))
+            for i, n in enumerate((700, 1500, 90, 2300, 411))]
+    rng = np.random.default_rng(61)
+    for A in mats:
+        A.vals = OP.stored_values(A.vals, store)
+    Ms = [CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, C.csrk_tune_rhs(A.n, A.nnz, nrhs, "mi355x"), store),
+                     store) for A in mats]
+    B = CsrkBatch(Ms)
+    dt = torch.float64 if store == "f64" else torch.float32
+    Xs, Gs = [], []
+    for A in mats:
+        shp = (A.n,) if nrhs == 1 else (A.n, nrhs)
+        X, G = rng.uniform(-1, 1, shp), rng.uniform(-1, 1, shp)
+        if store != "f64":
+            X, G = X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
+        Xs.append(X)
+        Gs.append(G)
+    xs = [to_dev(X[M.structure()["perm"]], dt) for X, M in zip(Xs, Ms)]
+    gs = [to_dev(G[M.structure()["perm"]], dt) for G, M in zip(Gs, Ms)]
+    vals = [M.values() for M in Ms] if explicit_vals else None
+    say("batch adjoint", store, nrhs, explicit_vals)
+    gxs, gvs = B.adjoint(xs, gs, vals=vals)
+    torch.cuda.synchronize()
+    for i, (A, M) in enumerate(zip(mats, Ms)):
+        s = M.structure()
+        perm, vmap = s["perm"], s["vmap"]
+        gx_in = np.empty(gxs[i].shape)
+        gx_in[perm] = gxs[i].double().cpu().numpy()
+        gv_in = np.empty(A.nnz)
+        gv_in[vmap] = gvs[i].double().cpu().numpy()
+        ref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, Gs[i])
+        scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(Gs[i]))
+        cc = np.maximum(np.bincount(A.col_idx, minlength=A.n), 1)
+        cc = cc if nrhs == 1 else cc[:, None]
+        beta = 1e-12 if store == "f64" else OP.gamma(cc, 2.0 ** -24)
+        assert np.all(np.abs(gx_in - ref) <= beta * scale), (i, store, nrhs)
+        refv = OA.grad_vals(A.row_ptr, A.col_idx, Xs[i], Gs[i])
+        if nrhs == 1:
+            # one rounded product per entry: bitwise in every precision
+            refv = refv if store == "f64" else refv.astype(np.float32).astype(np.float64)
+            assert np.array_equal(gv_in, refv), (i, store)
+        else:
+            scalev = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(Xs[i]), np.abs(Gs[i]))
+            betav = 1e-12 if store == "f64" else OP.gamma(nrhs, 2.0 ** -24)
+            assert np.all(np.abs(gv_in - refv) <= betav * scalev), (i, store)
+        gx1, gv1 = M.adjoint(xs[i], gs[i], vals=None if vals is None else vals[i])
+        torch.cuda.synchronize()
+        assert torch.equal(gv1, gvs[i]), (i, "grad_vals differs from the single-matrix launch")

@@ -43,18 +43,39 @@ def test_cg_f64_matches_oracle():
     assert np.max(np.abs(x - xo)) <= 1e-8 * np.max(np.abs(xo))
 
 
-@pytest.mark.parametrize("store,rtol,true_tol", [("f32", 1e-6, 1e-5), ("bf16", 1e-6, 3e-2)])
-def test_cg_reduced_precision_storage(store, rtol, true_tol):
+@pytest.mark.parametrize("store", ["f32", "bf16"])
+def test_cg_reduced_precision_storage(store):
+    """Values that the storage type cannot hold (4.1 / -0.9, still symmetric positive definite): the recurrence converges on the stored
+    matrix; against the FP64 values the storage rounding remains, and the true residual is bounded by
+    ||b - A_s x|| + || |A - A_s| |x| || (A_s the stored matrix), computed from the oracle in FP64."""
     A = _spd()
+    A.vals = np.where(A.vals > 0, 4.1, -0.9)
     b = np.random.default_rng(2).uniform(-1, 1, A.n)
+    rtol = 1e-6
     say("cg", store)
     x, it, rel, _ = _solve(A, store, b, rtol)
     assert rel <= rtol
-    # the recurrence solves the stored matrix; against the FP64 matrix the storage rounding remains
     stored = OP.stored_values(A.vals, store)
-    r_stored = np.linalg.norm(b - OS.spmv(A.row_ptr, A.col_idx, stored, x)) / np.linalg.norm(b)
-    r_true = np.linalg.norm(b - OS.spmv(A.row_ptr, A.col_idx, A.vals, x)) / np.linalg.norm(b)
-    assert r_stored <= 1e-4 and r_true <= true_tol, (r_stored, r_true)
+    assert not np.array_equal(stored, A.vals)
+    nb = np.linalg.norm(b)
+    r_stored = np.linalg.norm(b - OS.spmv(A.row_ptr, A.col_idx, stored, x)) / nb
+    r_true = np.linalg.norm(b - OS.spmv(A.row_ptr, A.col_idx, A.vals, x)) / nb
+    pert = np.linalg.norm(OS.spmv(A.row_ptr, A.col_idx, np.abs(A.vals - stored), np.abs(x))) / nb
+    # the recurrence residual drifts from the true one of the stored matrix by the FP32 rounding of the products
+    # and of the direction vector: bounded here by 100x the recurrence tolerance
+    assert r_stored <= 100 * rtol, r_stored
+    assert r_true <= r_stored + pert * (1 + 1e-12), (r_true, r_stored, pert)
+
+
+def test_cg_bf16_equals_f32_when_values_are_exact():
+    """4 / -1 values are exact in BF16 and FP32: both storages feed the same FP32 products in the same order, so
+    the two solves agree bit for bit."""
+    A = _spd()
+    b = np.random.default_rng(2).uniform(-1, 1, A.n)
+    say("cg bf16 == f32")
+    x32, it32, rel32, _ = _solve(A, "f32", b, 1e-6)
+    x16, it16, rel16, _ = _solve(A, "bf16", b, 1e-6)
+    assert it32 == it16 and rel32 == rel16 and np.array_equal(x32, x16)
 
 
 def test_cg_deterministic_initial_guess_and_csr2():
