@@ -342,6 +342,17 @@ csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *c
 csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const void *const *x, const void *const *g,
                                     void *const *grad_x, void *const *grad_vals, int32_t nrhs, void *stream);
 
+/*
+ * csrk_batch_set_launch — launch shape of a batch's kernels: at least
+ * blocks_per_cu workgroups per compute unit in the grid (0 = the library's
+ * default) and waves_per_wg wavefronts per workgroup (0 = keep the first
+ * handle's).  The grouping of the matrices is not changed.  Used by the
+ * autotuner.  Must not overlap calls in flight on the batch.
+ * Errors: CSRK_ERR_ARG (null batch, blocks_per_cu outside 0..256,
+ * waves_per_wg outside 0..16).
+ */
+csrk_status csrk_batch_set_launch(csrk_batch b, int32_t blocks_per_cu, int32_t waves_per_wg);
+
 csrk_status csrk_batch_destroy(csrk_batch b);
 
 /*

@@ -92,6 +92,7 @@ _SIGS = {
                         ctypes.c_int),
     "csrk_batch_spmv_adjoint": ([_h, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp),
                                  ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int32, _vp], ctypes.c_int),
+    "csrk_batch_set_launch": ([_h, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "csrk_batch_destroy": ([_h], ctypes.c_int),
     "csrk_probe_read": ([_vp, ctypes.c_int64, _vp, _vp], ctypes.c_int),
     "csrk_probe_copy": ([_vp, _vp, ctypes.c_int64, _vp], ctypes.c_int),
@@ -333,6 +334,10 @@ def csrk_batch_spmv(b: int, vals, x, y, nrhs: int, stream):
 def csrk_batch_spmv_adjoint(b: int, vals, x, g, grad_x, grad_vals, nrhs: int, stream):
     _check(lib().csrk_batch_spmv_adjoint(b, _ptr_array(vals), _ptr_array(x), _ptr_array(g), _ptr_array(grad_x),
                                          _ptr_array(grad_vals), int(nrhs), stream), "csrk_batch_spmv_adjoint")
+
+
+def csrk_batch_set_launch(b: int, blocks_per_cu: int = 0, waves_per_wg: int = 0):
+    _check(lib().csrk_batch_set_launch(b, int(blocks_per_cu), int(waves_per_wg)), "csrk_batch_set_launch")
 
 
 def csrk_batch_destroy(b: int):

@@ -300,6 +300,104 @@ def grid_markdown(res: SweepResult, picks: dict, command: str) -> str:
     return "\n".join(lines) + "\n"
 
 
+@dataclass
+class BatchTrial:
+    srs: int
+    ssrs: int
+    blocks_per_cu: int
+    fwd_us: float
+    adj_us: float
+
+    @property
+    def us(self) -> float:
+        return self.fwd_us + self.adj_us
+
+
+def sweep_batch(mats, store: str = "f32", nrhs: int = 8, srs_list=(32, 48, 64, 96), ssrs_list=(4, 8, 16),
+                blocks_list=(4, 8, 16, 32), reps: int = 20, warmup: int = 5, seed: int = 0, threads: int = 16,
+                extra=()) -> list:
+    """The batched multi-right-hand-side objective: for every (SRS, SSRS) every matrix of the batch is rebuilt
+    with those sizes (one super-row per wavefront: waves = SSRS, at most 16) and, for every grid size in
+    workgroups per CU, the forward and the adjoint launches are timed (mean event time of `reps` back-to-back
+    runs after `warmup`).  ``extra``: further (srs, ssrs, blocks_per_cu) points to time (a model's pick)."""
+    from .matrix import CsrkBatch
+    dt = torch.float64 if store == "f64" else torch.float32
+    g = torch.Generator(device="cuda").manual_seed(seed)
+    trials = []
+    wanted = {}
+    for srs, ssrs in itertools.product(srs_list, ssrs_list):
+        wanted[(srs, ssrs)] = set(blocks_list)
+    for srs, ssrs, blocks in extra:
+        wanted.setdefault((srs, ssrs), set()).add(blocks)
+    lib = C.lib()
+    st = torch.cuda.current_stream().cuda_stream
+    for (srs, ssrs), blocks_set in wanted.items():
+        def build(A):
+            p = C.csrk_tune_rhs(len(A.row_ptr) - 1, int(A.row_ptr[-1]), nrhs, "mi355x")
+            p.update(srs=srs, ssrs=ssrs, waves_per_wg=min(ssrs, 16))
+            return C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, p)
+        with cf.ThreadPoolExecutor(threads) as ex:
+            hs = list(ex.map(build, mats))
+        Ms = []
+        for h in hs:
+            C.csrk_upload(h, store)
+            Ms.append(CsrkMatrix(h, store))
+        B = CsrkBatch(Ms)
+        shape = lambda M: (M.n, nrhs) if nrhs > 1 else (M.n,)  # noqa: E731
+        X = [torch.rand(shape(M), generator=g, device="cuda", dtype=dt) * 2 - 1 for M in Ms]
+        G = [torch.rand(shape(M), generator=g, device="cuda", dtype=dt) * 2 - 1 for M in Ms]
+        Y = [torch.empty_like(x) for x in X]
+        GX = [torch.empty_like(x) for x in X]
+        GV = [torch.empty(M.nnz, device="cuda", dtype=dt) for M in Ms]
+        arr = C._ptr_array
+        px, py, pg = arr([t.data_ptr() for t in X]), arr([t.data_ptr() for t in Y]), arr([t.data_ptr() for t in G])
+        pgx, pgv = arr([t.data_ptr() for t in GX]), arr([t.data_ptr() for t in GV])
+        fwd = lambda: lib.csrk_batch_spmv(B.handle, None, px, py, nrhs, st)  # noqa: E731
+        adj = lambda: lib.csrk_batch_spmv_adjoint(B.handle, None, px, pg, pgx, pgv, nrhs, st)  # noqa: E731
+        for blocks in sorted(blocks_set):
+            C.csrk_batch_set_launch(B.handle, blocks, 0)
+            times = []
+            for f in (fwd, adj):
+                for _ in range(warmup):
+                    if f():
+                        raise RuntimeError(C.csrk_last_error_detail())
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                for _ in range(reps):
+                    f()
+                b.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(b) * 1e3 / reps)
+            trials.append(BatchTrial(srs, ssrs, blocks, times[0], times[1]))
+            print(f"batch SRS {srs} SSRS {ssrs} blocks/CU {blocks}: forward {times[0]:.1f} us, adjoint "
+                  f"{times[1]:.1f} us", flush=True)
+        B.close()
+        for M in Ms:
+            M.close()
+    return trials
+
+
+def batch_markdown(trials, model: tuple, command: str, label: str) -> str:
+    """The batched sweep: every point, the optimum, and the model's pick against it."""
+    best = min(trials, key=lambda t: t.us)
+    pick = next((t for t in trials if (t.srs, t.ssrs, t.blocks_per_cu) == model), None)
+    lines = [f"Batched multi-right-hand-side sweep on {label}: forward + adjoint launch times (mean of back-to-back "
+             "runs, event-timed), one point per (SRS, SSRS, workgroups per CU); waves per workgroup = SSRS.", "",
+             "Command:", "", "    " + command, "",
+             "| SRS | SSRS | workgroups/CU | forward us | adjoint us | step us | / optimum |",
+             "|---|---|---|---|---|---|---|"]
+    for t in sorted(trials, key=lambda t: (t.srs, t.ssrs, t.blocks_per_cu)):
+        mark = " **optimum**" if t is best else (" model" if t is pick else "")
+        lines.append(f"| {t.srs} | {t.ssrs} | {t.blocks_per_cu} | {t.fwd_us:.1f} | {t.adj_us:.1f} | {t.us:.1f} | "
+                     f"{t.us / best.us:.3f}{mark} |")
+    lines += ["", f"Optimum: SRS {best.srs}, SSRS {best.ssrs}, {best.blocks_per_cu} workgroups per CU: "
+                  f"{best.us:.1f} us per step."]
+    if pick is not None:
+        lines.append(f"Model pick (SRS {model[0]}, SSRS {model[1]}, {model[2]} workgroups per CU): {pick.us:.1f} us, "
+                     f"{pick.us / best.us:.3f} x the optimum.")
+    return "\n".join(lines) + "\n"
+
+
 def main(argv=None):
     import os
     ap = argparse.ArgumentParser(description=__doc__)
@@ -315,7 +413,27 @@ def main(argv=None):
     ap.add_argument("--srs", default=None, help="comma-separated SRS values (with --workload)")
     ap.add_argument("--ssrs", default=None, help="comma-separated SSRS values (with --workload)")
     ap.add_argument("--lanes", default="1,2,4", help="comma-separated lanes per row (with --workload)")
+    ap.add_argument("--batch", default=None, help="sweep a batched workload of gen (e.g. c5): SRS x SSRS x grid")
+    ap.add_argument("--blocks", default="4,8,16,32", help="comma-separated workgroups per CU (with --batch)")
     args = ap.parse_args(argv)
+    if args.batch:
+        sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+        import gen
+        w = gen.WORKLOADS[args.batch]()
+        ints = lambda v, d: tuple(int(t) for t in v.split(",")) if v else d  # noqa: E731
+        mats, nrhs = w["As"], w["nrhs"]
+        p = C.csrk_tune_rhs(mats[0].n, mats[0].nnz, nrhs, "mi355x")
+        model = (p["srs"], p["ssrs"], 16)
+        trials = sweep_batch(mats, w["dtype"], nrhs, ints(args.srs, (32, 48, 64, 96)), ints(args.ssrs, (4, 8, 16)),
+                             ints(args.blocks, (4, 8, 16, 32)), extra=[model])
+        cmd = "python -m paper_2203_05096_amd.autotune " + " ".join(argv if argv is not None else sys.argv[1:])
+        text = batch_markdown(trials, model, cmd, f"{args.batch} ({len(mats)} matrices, {nrhs} right-hand sides, "
+                                                  f"{w['dtype']})")
+        print(text, flush=True)
+        if args.markdown:
+            with open(args.markdown, "w") as f:
+                f.write(text)
+        return
     if args.workload:
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
         import gen

@@ -57,6 +57,7 @@ struct csrk_batch_s {
     bool last_valid[2] = {false, false};
     csrk::dev::Shape shape;
     int cus = 0;
+    int blocks_per_cu = 0;  // 0: the library's default (kBatchBlocksPerCu)
 };
 
 namespace {
@@ -840,7 +841,8 @@ bool all_aligned16(std::initializer_list<const void *const *> arrays, size_t cou
 constexpr int kBatchBlocksPerCu = 16;
 
 int batch_grid(csrk_batch b, int nrhs, bool adj, bool ind, bool vec) {
-    const int per_cu = std::max(kBatchBlocksPerCu, csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj, ind, vec));
+    const int want = b->blocks_per_cu > 0 ? b->blocks_per_cu : kBatchBlocksPerCu;
+    const int per_cu = std::max(want, csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj, ind, vec));
     const int64_t g = int64_t(b->cus) * per_cu;
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, b->nitems)));
 }
@@ -907,6 +909,17 @@ csrk_status csrk_probe_copy(const void *src_dev, void *dst_dev, int64_t bytes, v
         check_align16(src_dev, "src_dev");
         check_align16(dst_dev, "dst_dev");
         hip_check(csrk::dev::probe_copy(src_dev, dst_dev, bytes, static_cast<hipStream_t>(stream)), "csrk_probe_copy");
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_batch_set_launch(csrk_batch b, int32_t blocks_per_cu, int32_t waves_per_wg) {
+    return guard([&] {
+        if (!b) throw Error{CSRK_ERR_ARG, "null batch"};
+        if (blocks_per_cu < 0 || blocks_per_cu > 256) throw Error{CSRK_ERR_ARG, "blocks_per_cu must be in 0..256"};
+        if (waves_per_wg < 0 || waves_per_wg > 16) throw Error{CSRK_ERR_ARG, "waves_per_wg must be in 0..16"};
+        b->blocks_per_cu = blocks_per_cu;
+        if (waves_per_wg > 0) b->shape.waves = waves_per_wg;
         return CSRK_OK;
     });
 }

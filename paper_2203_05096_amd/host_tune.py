@@ -63,12 +63,16 @@ def sweep_host(A, srs_list=None, reps: int = 20, warmup: int = 5, nthreads: int 
     trials = []
     with cf.ThreadPoolExecutor(build_threads) as ex:
         for i in range(0, len(srs_list), build_threads):
-            for srs, h in ex.map(build, srs_list[i:i + build_threads]):
+            # every build of the chunk finishes before any timing starts: builds running beside the timed
+            # kernel would take cores from it
+            built = list(ex.map(build, srs_list[i:i + build_threads]))
+            for j, (srs, h) in enumerate(built):
                 try:
                     perm = C.csrk_copy_structure(h)["perm"]
                     trials.append((srs, time_host(h, x[perm], reps, warmup, nthreads)))
                 finally:
                     C.csrk_destroy(h)
+                    built[j] = (srs, None)
     best = min(trials, key=lambda t: t[1])
     fixed = C.csrk_tune(len(A.row_ptr) - 1, int(A.row_ptr[-1]), "host_cpu")
     at_fixed = next((us for srs, us in trials if srs == fixed["srs"]), None)
