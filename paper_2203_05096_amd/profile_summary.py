@@ -53,6 +53,9 @@ def _rows(d: str, suffix: str):
 
 def short(name: str) -> str:
     """Kernel name without the argument list (template arguments kept)."""
+    name = name.replace("csrk::dev::(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
     depth = 0
     for i, ch in enumerate(name):
         if ch == "<":
