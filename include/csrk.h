@@ -285,9 +285,10 @@ csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nt
  * when ||r||_2 <= rtol * ||b||_2 (r the recurrence residual, checked every
  * check_every iterations) or after max_iter iterations; *iters_out and
  * *rel_resid_out (both may be NULL) receive the iteration count and
- * ||r||_2 / ||b||_2.  Allocates, for the call, 3 work vectors on the device
- * (4 with FP32/BF16 storage) and one FP64 partial sum per workgroup of the
- * product (p'Ap is summed by the product's own workgroups), and synchronises
+ * ||r||_2 / ||b||_2.  Allocates, for the call, one device block holding 3
+ * work vectors (4 with FP32/BF16 storage) and one FP64 partial sum per
+ * workgroup of the product (p'Ap is summed by the product's own workgroups),
+ * and synchronises
  * `stream` before returning.  Errors: CSRK_ERR_ARG (null
  * vectors, rtol <= 0, max_iter < 0, check_every < 1), CSRK_ERR_UNSUPPORTED on
  * a breakdown (p'A p <= 0: the stored matrix is not positive definite),
@@ -295,6 +296,30 @@ csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nt
  */
 csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
                     int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out);
+
+/*
+ * csrk_cg_noalloc — csrk_cg for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, hosts that forbid
+ * allocation during a solve).  Same arguments, iteration, results and errors
+ * as csrk_cg, bit for bit, but the work vectors, partial sums and scalars live
+ * in one fixed array of CSRK_CG_NOALLOC_BYTES bytes per device, owned by the
+ * library, created when the library's code is loaded on the device and held
+ * until the process ends; the call makes no device allocation or free.
+ * csrk_cg_noalloc_bytes reports the work memory a handle needs (3 or 4
+ * vectors of n entries, one FP64 partial sum per workgroup of the product,
+ * rounded to 256-byte boundaries); a handle that needs more than
+ * CSRK_CG_NOALLOC_BYTES (FP64 and FP32/BF16 storage alike: about
+ * 2.7 million rows) is rejected with CSRK_ERR_ARG before any device work.
+ * Every call on one device shares that device's array: calls that overlap in
+ * time on one device (different host threads, or different streams) race and
+ * give wrong results; the caller orders them.  The array keeps the last
+ * call's contents; nothing in it needs clearing, since each solve writes every
+ * work entry before reading it.  Synchronises `stream` before returning.
+ */
+#define CSRK_CG_NOALLOC_BYTES (64ll << 20)
+csrk_status csrk_cg_noalloc_bytes(csrk_handle h, int64_t *bytes_out);
+csrk_status csrk_cg_noalloc(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
+                            int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out);
 
 /*
  * csrk_spmv_adjoint — gradients of L = <g', A' x'> (not in the paper):

@@ -69,6 +69,9 @@ _SIGS = {
     "csrk_spmv_host": ([_h, _f64p, _f64p, ctypes.c_int32], ctypes.c_int),
     "csrk_cg": ([_h, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.POINTER(ctypes.c_int32),
                  ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "csrk_cg_noalloc": ([_h, _vp, _vp, ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _vp,
+                         ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "csrk_cg_noalloc_bytes": ([_h, _i64p], ctypes.c_int),
     "csrk_build_host": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _vp, ctypes.c_int,
                          ctypes.POINTER(csrk_params), ctypes.POINTER(_h)], ctypes.c_int),
     "csrk_build_from_groups": ([ctypes.c_int32, ctypes.c_int64, _i32p, _i32p, _vp, ctypes.c_int, _i32p, ctypes.c_int32,
@@ -294,6 +297,26 @@ def csrk_cg(h: int, b_dev, x_dev, rtol: float, max_iter: int, check_every: int, 
     _check(lib().csrk_cg(h, b_dev, x_dev, float(rtol), int(max_iter), int(check_every), stream, ctypes.byref(it),
                          ctypes.byref(rr)), "csrk_cg")
     return it.value, rr.value
+
+
+def csrk_cg_noalloc(h: int, b_dev, x_dev, rtol: float, max_iter: int, check_every: int, stream):
+    """Runs csrk_cg_noalloc (work memory in the library's fixed per-device array); returns (iterations, relative
+    recurrence residual)."""
+    it = ctypes.c_int32(0)
+    rr = ctypes.c_double(0.0)
+    _check(lib().csrk_cg_noalloc(h, b_dev, x_dev, float(rtol), int(max_iter), int(check_every), stream,
+                                 ctypes.byref(it), ctypes.byref(rr)), "csrk_cg_noalloc")
+    return it.value, rr.value
+
+
+def csrk_cg_noalloc_bytes(h: int) -> int:
+    """Device work memory csrk_cg_noalloc needs for this handle, in bytes."""
+    b = ctypes.c_int64(0)
+    _check(lib().csrk_cg_noalloc_bytes(h, ctypes.byref(b)), "csrk_cg_noalloc_bytes")
+    return b.value
+
+
+CG_NOALLOC_BYTES = 64 << 20  # CSRK_CG_NOALLOC_BYTES
 
 
 def csrk_spmv_plain(h: int, vals_dev, x_dev, y_dev, nrhs: int, stream):

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <initializer_list>
+#include <mutex>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -584,86 +585,183 @@ csrk_status csrk_spmv(csrk_handle h, const void *vals_dev, const void *x_dev, vo
     });
 }
 
-// Device buffers of one CG solve, freed on every exit path.
-struct CgBuffers {
-    std::vector<void *> ptrs;
-    void *get(size_t bytes, const char *what) {
-        void *p = nullptr;
-        hip_check(hipMalloc(&p, std::max<size_t>(bytes, 16)), what);
-        ptrs.push_back(p);
-        return p;
+namespace {
+
+// Work memory of one CG solve: r and p (FP64), q (the product's output:
+// FP32 with FP32/BF16 storage), p_lo (FP32 copy of p feeding FP32/BF16
+// storage), one FP64 partial sum per workgroup of the largest reduction grid,
+// and the scalars.  Each array starts on a 256-byte boundary.
+struct CgWork {
+    double *r = nullptr, *p = nullptr;
+    void *q = nullptr;
+    float *p_lo = nullptr;
+    double *part = nullptr, *s = nullptr;
+};
+
+size_t round256(size_t b) { return (std::max<size_t>(b, 16) + 255) / 256 * 256; }
+
+// Bytes of CgWork for this handle, and the pointers inside base.
+size_t cg_work_layout(const csrk_matrix *h, unsigned char *base, CgWork *w) {
+    const size_t n = size_t(h->n);
+    const bool lo = h->store != CSRK_F64;
+    const int nparts = std::max(csrk::dev::kCgGrid, csrk::dev::spmv_grid(arrays_of(h)));
+    const size_t sizes[6] = {n * 8, n * 8, n * (lo ? 4 : 8), lo ? n * 4 : 0, size_t(nparts) * 8, 8 * 8};
+    size_t off[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+        off[i] = total;
+        total += sizes[i] ? round256(sizes[i]) : 0;
     }
-    ~CgBuffers() {
-        for (void *p : ptrs) (void)hipFree(p);
+    if (base && w) {
+        w->r = reinterpret_cast<double *>(base + off[0]);
+        w->p = reinterpret_cast<double *>(base + off[1]);
+        w->q = base + off[2];
+        w->p_lo = lo ? reinterpret_cast<float *>(base + off[3]) : nullptr;
+        w->part = reinterpret_cast<double *>(base + off[4]);
+        w->s = reinterpret_cast<double *>(base + off[5]);
+    }
+    return total;
+}
+
+// Checks shared by the CG entry points.
+void cg_check_args(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
+                   int32_t check_every) {
+    need_device(h);
+    if (!b_dev || !x_dev || !(rtol > 0) || max_iter < 0 || check_every < 1)
+        throw Error{CSRK_ERR_ARG, "need b, x, rtol > 0, max_iter >= 0, check_every >= 1"};
+    check_vec(b_dev, h, "b");
+    check_vec(x_dev, h, "x");
+}
+
+// The CG iteration on work memory w (the caller's device is current).  Every
+// work array is written before it is read (r by the residual, p by its first
+// update, q by the product, each partial sum by its workgroup, each scalar by
+// the reduction that produces it), so w needs no clearing.
+void cg_run(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter, int32_t check_every,
+            hipStream_t st, const CgWork &w, int32_t *iters_out, double *rel_resid_out) {
+    const int64_t n = h->n;
+    const bool lo = h->store != CSRK_F64;  // product vectors are FP32
+    const csrk::dev::Arrays a = arrays_of(h);
+    const csrk::dev::Shape shp = shape_of(h);
+    double *r = w.r, *p = w.p, *part = w.part, *s = w.s;
+    void *q = w.q;
+    float *p_lo = w.p_lo;
+    auto spmv = [&](const void *in) {
+        hip_check(csrk::dev::spmv(a, h->store, h->d_vals, in, q, 1, shp, st), "cg product");
+    };
+    // r = b - A x0, p = r, rr = r . r, bb = b . b
+    if (lo) hip_check(csrk::dev::cg_round(x_dev, p_lo, n, st), "cg round");
+    spmv(lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(x_dev));
+    hip_check(csrk::dev::cg_residual(b_dev, q, lo, r, n, part, s, st), "cg residual");
+    hip_check(csrk::dev::cg_norm2(b_dev, n, part, s, st), "cg norm");
+    hip_check(csrk::dev::cg_set_p(r, p, p_lo, s, n, false, st), "cg p");
+    double host_s[6] = {0, 0, 0, 0, 0, 0};
+    auto read_scalars = [&]() {
+        hip_check(hipMemcpyAsync(host_s, s, sizeof(host_s), hipMemcpyDeviceToHost, st), "cg read");
+        hip_check(hipStreamSynchronize(st), "cg sync");
+    };
+    read_scalars();
+    const double bnorm = std::sqrt(host_s[5]);
+    const double target = rtol * (bnorm > 0 ? bnorm : 1.0);
+    int32_t it = 0;
+    bool done = std::sqrt(host_s[0]) <= target;
+    // Per iteration: q = A p with p . q summed per workgroup of the product
+    // (no separate pass over p and q), alpha; r -= alpha q with r . r, beta;
+    // then x += alpha p and p = r + beta p in one pass over p.
+    while (!done && it < max_iter) {
+        hip_check(csrk::dev::spmv_dot(a, h->store, h->d_vals,
+                                      lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(p), q, p,
+                                      part, shp, st),
+                  "cg product");
+        hip_check(csrk::dev::cg_alpha_parts(part, csrk::dev::spmv_grid(a), s, st), "cg alpha");
+        hip_check(csrk::dev::cg_update_r(r, q, lo, n, part, s, st), "cg residual update");
+        hip_check(csrk::dev::cg_update_xp(x_dev, p, p_lo, r, s, n, st), "cg x and p update");
+        ++it;
+        if (it % check_every == 0 || it == max_iter) {
+            read_scalars();
+            if (!(host_s[1] > 0) || !std::isfinite(host_s[0]))
+                throw Error{CSRK_ERR_UNSUPPORTED,
+                            "CG breakdown (p'Ap <= 0 or a non-finite residual): the matrix is not symmetric "
+                            "positive definite in the stored precision"};
+            done = std::sqrt(host_s[0]) <= target;
+        }
+    }
+    if (iters_out) *iters_out = it;
+    if (rel_resid_out) *rel_resid_out = std::sqrt(host_s[0]) / (bnorm > 0 ? bnorm : 1.0);
+    hip_check(hipStreamSynchronize(st), "cg sync");
+}
+
+// Device work memory of one csrk_cg call, freed on every exit path.
+struct CgAlloc {
+    void *ptr = nullptr;
+    ~CgAlloc() {
+        if (ptr) (void)hipFree(ptr);
     }
 };
+
+// Work memory of csrk_cg_noalloc: one array per device, held until the
+// process ends.  In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current.
+constexpr size_t kCgScratchBytes = size_t(CSRK_CG_NOALLOC_BYTES);
+__device__ __align__(256) unsigned char scratch[kCgScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_dev[kMaxDevices] = {};
+
+unsigned char *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) throw Error{CSRK_ERR_DEVICE, "device index out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *ptr = nullptr;
+        hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "csrk_cg_noalloc scratch address");
+        if (!ptr) throw Error{CSRK_ERR_DEVICE, "csrk_cg_noalloc: no device address for the scratch array"};
+        g_scratch_dev[device] = static_cast<unsigned char *>(ptr);
+    }
+    return g_scratch_dev[device];
+}
+
+}  // namespace
 
 csrk_status csrk_cg(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
                     int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out) {
     return guard([&] {
-        need_device(h);
-        if (!b_dev || !x_dev || !(rtol > 0) || max_iter < 0 || check_every < 1)
-            throw Error{CSRK_ERR_ARG, "need b, x, rtol > 0, max_iter >= 0, check_every >= 1"};
-        check_vec(b_dev, h, "b");
-        check_vec(x_dev, h, "x");
+        cg_check_args(h, b_dev, x_dev, rtol, max_iter, check_every);
         DeviceScope ds(h->device);
-        hipStream_t st = static_cast<hipStream_t>(stream);
-        const int64_t n = h->n;
-        const bool lo = h->store != CSRK_F64;  // product vectors are FP32
-        const csrk::dev::Arrays a = arrays_of(h);
-        const csrk::dev::Shape shp = shape_of(h);
-        CgBuffers buf;
-        double *r = static_cast<double *>(buf.get(size_t(n) * 8, "cg r"));
-        double *p = static_cast<double *>(buf.get(size_t(n) * 8, "cg p"));
-        void *q = buf.get(size_t(n) * (lo ? 4 : 8), "cg q");
-        float *p_lo = lo ? static_cast<float *>(buf.get(size_t(n) * 4, "cg p (fp32)")) : nullptr;
-        // partial sums: kCgGrid for the vector kernels, one per workgroup of the product
-        const int nparts = std::max(csrk::dev::kCgGrid, csrk::dev::spmv_grid(a));
-        double *part = static_cast<double *>(buf.get(size_t(nparts) * 8, "cg partial sums"));
-        double *s = static_cast<double *>(buf.get(8 * 8, "cg scalars"));
-        auto spmv = [&](const void *in) {
-            hip_check(csrk::dev::spmv(a, h->store, h->d_vals, in, q, 1, shp, st), "cg product");
-        };
-        // r = b - A x0, p = r, rr = r . r, bb = b . b
-        if (lo) hip_check(csrk::dev::cg_round(x_dev, p_lo, n, st), "cg round");
-        spmv(lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(x_dev));
-        hip_check(csrk::dev::cg_residual(b_dev, q, lo, r, n, part, s, st), "cg residual");
-        hip_check(csrk::dev::cg_norm2(b_dev, n, part, s, st), "cg norm");
-        hip_check(csrk::dev::cg_set_p(r, p, p_lo, s, n, false, st), "cg p");
-        double host_s[6] = {0, 0, 0, 0, 0, 0};
-        auto read_scalars = [&]() {
-            hip_check(hipMemcpyAsync(host_s, s, sizeof(host_s), hipMemcpyDeviceToHost, st), "cg read");
-            hip_check(hipStreamSynchronize(st), "cg sync");
-        };
-        read_scalars();
-        const double bnorm = std::sqrt(host_s[5]);
-        const double target = rtol * (bnorm > 0 ? bnorm : 1.0);
-        int32_t it = 0;
-        bool done = std::sqrt(host_s[0]) <= target;
-        // Per iteration: q = A p with p . q summed per workgroup of the product
-        // (no separate pass over p and q), alpha; r -= alpha q with r . r, beta;
-        // then x += alpha p and p = r + beta p in one pass over p.
-        while (!done && it < max_iter) {
-            hip_check(csrk::dev::spmv_dot(a, h->store, h->d_vals,
-                                          lo ? static_cast<const void *>(p_lo) : static_cast<const void *>(p), q, p,
-                                          part, shp, st),
-                      "cg product");
-            hip_check(csrk::dev::cg_alpha_parts(part, csrk::dev::spmv_grid(a), s, st), "cg alpha");
-            hip_check(csrk::dev::cg_update_r(r, q, lo, n, part, s, st), "cg residual update");
-            hip_check(csrk::dev::cg_update_xp(x_dev, p, p_lo, r, s, n, st), "cg x and p update");
-            ++it;
-            if (it % check_every == 0 || it == max_iter) {
-                read_scalars();
-                if (!(host_s[1] > 0) || !std::isfinite(host_s[0]))
-                    throw Error{CSRK_ERR_UNSUPPORTED,
-                                "CG breakdown (p'Ap <= 0 or a non-finite residual): the matrix is not symmetric "
-                                "positive definite in the stored precision"};
-                done = std::sqrt(host_s[0]) <= target;
-            }
-        }
-        if (iters_out) *iters_out = it;
-        if (rel_resid_out) *rel_resid_out = std::sqrt(host_s[0]) / (bnorm > 0 ? bnorm : 1.0);
-        hip_check(hipStreamSynchronize(st), "cg sync");
+        const size_t bytes = cg_work_layout(h, nullptr, nullptr);
+        CgAlloc mem;
+        hip_check(hipMalloc(&mem.ptr, bytes), "cg work vectors");
+        CgWork w;
+        cg_work_layout(h, static_cast<unsigned char *>(mem.ptr), &w);
+        cg_run(h, b_dev, x_dev, rtol, max_iter, check_every, static_cast<hipStream_t>(stream), w, iters_out,
+               rel_resid_out);
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_cg_noalloc_bytes(csrk_handle h, int64_t *bytes_out) {
+    return guard([&] {
+        if (!h || !bytes_out) throw Error{CSRK_ERR_ARG, "null argument"};
+        need_device(h);
+        *bytes_out = static_cast<int64_t>(cg_work_layout(h, nullptr, nullptr));
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_cg_noalloc(csrk_handle h, const double *b_dev, double *x_dev, double rtol, int32_t max_iter,
+                            int32_t check_every, void *stream, int32_t *iters_out, double *rel_resid_out) {
+    return guard([&] {
+        cg_check_args(h, b_dev, x_dev, rtol, max_iter, check_every);
+        const size_t bytes = cg_work_layout(h, nullptr, nullptr);
+        if (bytes > kCgScratchBytes)
+            throw Error{CSRK_ERR_ARG, "csrk_cg_noalloc: the solve needs " + std::to_string(bytes) +
+                                          " bytes of work memory, more than its fixed " +
+                                          std::to_string(kCgScratchBytes) + "-byte array; use csrk_cg"};
+        DeviceScope ds(h->device);
+        CgWork w;
+        cg_work_layout(h, scratch_on(h->device), &w);
+        cg_run(h, b_dev, x_dev, rtol, max_iter, check_every, static_cast<hipStream_t>(stream), w, iters_out,
+               rel_resid_out);
         return CSRK_OK;
     });
 }
