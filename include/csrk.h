@@ -369,9 +369,10 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
 
 /*
  * csrk_batch_set_launch — launch shape of a batch's kernels: at least
- * blocks_per_cu workgroups per compute unit in the grid (0 = the library's
- * default) and waves_per_wg wavefronts per workgroup (0 = keep the first
- * handle's).  The grouping of the matrices is not changed.  Used by the
+ * blocks_per_cu workgroups per compute unit in the grid, each taking a
+ * contiguous range of (matrix, super-super-row) items (0 = the library's
+ * default: one workgroup per item), and waves_per_wg wavefronts per
+ * workgroup (0 = keep the first handle's).  The grouping of the matrices is not changed.  Used by the
  * autotuner.  Must not overlap calls in flight on the batch.
  * Errors: CSRK_ERR_ARG (null batch, blocks_per_cu outside 0..256,
  * waves_per_wg outside 0..16).

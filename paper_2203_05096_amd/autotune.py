@@ -314,11 +314,12 @@ class BatchTrial:
 
 
 def sweep_batch(mats, store: str = "f32", nrhs: int = 8, srs_list=(32, 48, 64, 96), ssrs_list=(4, 8, 16),
-                blocks_list=(4, 8, 16, 32), reps: int = 20, warmup: int = 5, seed: int = 0, threads: int = 16,
+                blocks_list=(0, 16, 64), reps: int = 20, warmup: int = 5, seed: int = 0, threads: int = 16,
                 extra=()) -> list:
     """The batched multi-right-hand-side objective: for every (SRS, SSRS) every matrix of the batch is rebuilt
     with those sizes (one super-row per wavefront: waves = SSRS, at most 16) and, for every grid size in
-    workgroups per CU, the forward and the adjoint launches are timed (mean event time of `reps` back-to-back
+    workgroups per CU (0: one workgroup per (matrix, SSR) item, the library's default), the forward and the
+    adjoint launches are timed (mean event time of `reps` back-to-back
     runs after `warmup`).  ``extra``: further (srs, ssrs, blocks_per_cu) points to time (a model's pick)."""
     from .matrix import CsrkBatch
     dt = torch.float64 if store == "f64" else torch.float32
@@ -369,7 +370,7 @@ def sweep_batch(mats, store: str = "f32", nrhs: int = 8, srs_list=(32, 48, 64, 9
                 torch.cuda.synchronize()
                 times.append(a.elapsed_time(b) * 1e3 / reps)
             trials.append(BatchTrial(srs, ssrs, blocks, times[0], times[1]))
-            print(f"batch SRS {srs} SSRS {ssrs} blocks/CU {blocks}: forward {times[0]:.1f} us, adjoint "
+            print(f"batch SRS {srs} SSRS {ssrs} blocks/CU {blocks or 'one per item'}: forward {times[0]:.1f} us, adjoint "
                   f"{times[1]:.1f} us", flush=True)
         B.close()
         for M in Ms:
@@ -388,12 +389,13 @@ def batch_markdown(trials, model: tuple, command: str, label: str) -> str:
              "|---|---|---|---|---|---|---|"]
     for t in sorted(trials, key=lambda t: (t.srs, t.ssrs, t.blocks_per_cu)):
         mark = " **optimum**" if t is best else (" model" if t is pick else "")
-        lines.append(f"| {t.srs} | {t.ssrs} | {t.blocks_per_cu} | {t.fwd_us:.1f} | {t.adj_us:.1f} | {t.us:.1f} | "
+        lines.append(f"| {t.srs} | {t.ssrs} | {t.blocks_per_cu or 'one per item'} | {t.fwd_us:.1f} | {t.adj_us:.1f} | {t.us:.1f} | "
                      f"{t.us / best.us:.3f}{mark} |")
-    lines += ["", f"Optimum: SRS {best.srs}, SSRS {best.ssrs}, {best.blocks_per_cu} workgroups per CU: "
+    lines += ["", f"Optimum: SRS {best.srs}, SSRS {best.ssrs}, workgroups per CU {best.blocks_per_cu or 'one per item'}: "
                   f"{best.us:.1f} us per step."]
     if pick is not None:
-        lines.append(f"Model pick (SRS {model[0]}, SSRS {model[1]}, {model[2]} workgroups per CU): {pick.us:.1f} us, "
+        lines.append(f"Model pick (SRS {model[0]}, SSRS {model[1]}, workgroups per CU {model[2] or 'one per item'}): "
+                     f"{pick.us:.1f} us, "
                      f"{pick.us / best.us:.3f} x the optimum.")
     return "\n".join(lines) + "\n"
 
@@ -414,7 +416,8 @@ def main(argv=None):
     ap.add_argument("--ssrs", default=None, help="comma-separated SSRS values (with --workload)")
     ap.add_argument("--lanes", default="1,2,4", help="comma-separated lanes per row (with --workload)")
     ap.add_argument("--batch", default=None, help="sweep a batched workload of gen (e.g. c5): SRS x SSRS x grid")
-    ap.add_argument("--blocks", default="4,8,16,32", help="comma-separated workgroups per CU (with --batch)")
+    ap.add_argument("--blocks", default="0,16,64",
+                    help="comma-separated workgroups per CU (with --batch; 0 = one workgroup per work item)")
     args = ap.parse_args(argv)
     if args.batch:
         sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
@@ -423,9 +426,9 @@ def main(argv=None):
         ints = lambda v, d: tuple(int(t) for t in v.split(",")) if v else d  # noqa: E731
         mats, nrhs = w["As"], w["nrhs"]
         p = C.csrk_tune_rhs(mats[0].n, mats[0].nnz, nrhs, "mi355x")
-        model = (p["srs"], p["ssrs"], 16)
+        model = (p["srs"], p["ssrs"], 0)  # the library's default grid: one workgroup per work item
         trials = sweep_batch(mats, w["dtype"], nrhs, ints(args.srs, (32, 48, 64, 96)), ints(args.ssrs, (4, 8, 16)),
-                             ints(args.blocks, (4, 8, 16, 32)), extra=[model])
+                             ints(args.blocks, (0, 16, 64)), extra=[model])
         cmd = "python -m paper_2203_05096_amd.autotune " + " ".join(argv if argv is not None else sys.argv[1:])
         text = batch_markdown(trials, model, cmd, f"{args.batch} ({len(mats)} matrices, {nrhs} right-hand sides, "
                                                   f"{w['dtype']})")

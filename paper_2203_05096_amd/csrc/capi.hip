@@ -58,7 +58,8 @@ struct csrk_batch_s {
     bool last_valid[2] = {false, false};
     csrk::dev::Shape shape;
     int cus = 0;
-    int blocks_per_cu = 0;  // 0: the library's default (kBatchBlocksPerCu)
+    int blocks_per_cu = 0;  // 0: one workgroup per work item (batch_grid)
+    bool all_sym = true;    // every handle's pattern is symmetric
 };
 
 namespace {
@@ -850,6 +851,7 @@ csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_ba
                 const int32_t nssr = static_cast<int32_t>(handles[b]->ssr_ptr.size()) - 1;
                 for (int32_t t = 0; t < nssr; ++t) items.push_back(make_int2(b, t));
                 bt->max_n = std::max(bt->max_n, handles[b]->n);
+                bt->all_sym = bt->all_sym && handles[b]->trans.symmetric;
             }
             if (items.size() > size_t(INT32_MAX)) throw Error{CSRK_ERR_ARG, "work list too long"};
             bt->nitems = static_cast<int32_t>(items.size());
@@ -930,17 +932,20 @@ bool all_aligned16(std::initializer_list<const void *const *> arrays, size_t cou
     return true;
 }
 
-// Workgroups per CU of a batched launch, at least.  Each workgroup takes a
-// contiguous range of the work list, and ranges differ in cost (matrices have
-// their own super-row sizes); launching several times the workgroups that fit
-// at once lets the dispatcher start a new range wherever one finishes.  On the
-// 64-matrix multi-RHS set, 16 per CU measured best of 2 to 64, about 8% faster
-// than one resident set of workgroups in both directions.
-constexpr int kBatchBlocksPerCu = 16;
-
-int batch_grid(csrk_batch b, int nrhs, bool adj, bool ind, bool vec) {
-    const int want = b->blocks_per_cu > 0 ? b->blocks_per_cu : kBatchBlocksPerCu;
-    const int per_cu = std::max(want, csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj, ind, vec));
+// Grid of a batched launch.  By default one workgroup per (matrix, SSR) work
+// item: workgroups are dispatched in order and each XCD takes a contiguous
+// range of items, so the workgroups resident on an XCD at any time work on
+// neighbouring super-super-rows and share their x (and g) rows in that XCD's
+// L2.  On the 64-matrix, 8-right-hand-side set this measured 15% faster in
+// both directions than 16 workgroups per CU each walking a contiguous range of
+// items (there, the resident workgroups of an XCD were spread over its whole
+// range and the L2 hit rate fell to about a third).  With blocks_per_cu > 0
+// (autotuner), the grid is at least that many workgroups per CU, each taking
+// a contiguous range of items.
+int batch_grid(csrk_batch b, int nrhs, bool adj, bool ind, bool vec, bool both) {
+    if (b->blocks_per_cu == 0) return std::max(1, b->nitems);
+    const int per_cu = std::max(b->blocks_per_cu, csrk::dev::batch_occupancy(b->store, nrhs, b->shape, adj, ind, vec,
+                                                                              b->all_sym, both));
     const int64_t g = int64_t(b->cus) * per_cu;
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(g, b->nitems)));
 }
@@ -961,7 +966,7 @@ csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *c
         csrk::dev::MatDesc *descs = upload_descs(b, 0, vals, x, y, nullptr, nullptr, nullptr, st);
         const bool vec = all_aligned16({x, reinterpret_cast<const void *const *>(y)}, b->handles.size());
         hip_check(csrk::dev::batch_forward(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
-                                           batch_grid(b, nrhs, false, false, vec), vec, st),
+                                           batch_grid(b, nrhs, false, false, vec, false), vec, st),
                   "csrk_batch_spmv launch");
         return CSRK_OK;
     });
@@ -983,8 +988,9 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         csrk::dev::MatDesc *descs = upload_descs(b, 1, vals, x, nullptr, g, grad_x, grad_vals, st);
         const bool ind = vals && std::any_of(vals, vals + b->handles.size(), [](const void *p) { return p != nullptr; });
         const bool vec = all_aligned16({x, g, reinterpret_cast<const void *const *>(grad_x)}, b->handles.size());
+        const bool both = grad_x && grad_vals;
         hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
-                                           batch_grid(b, nrhs, true, ind, vec), ind, vec, st),
+                                           batch_grid(b, nrhs, true, ind, vec, both), ind, vec, b->all_sym, both, st),
                   "csrk_batch_spmv_adjoint launch");
         return CSRK_OK;
     });

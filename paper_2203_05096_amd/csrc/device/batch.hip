@@ -45,7 +45,14 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
     }
 }
 
-template <typename VT, int L, int VX, bool IND>
+// Adjoint paths of a batched launch, one instantiation each so that a launch
+// carries only its own path's registers: one right-hand side (fused or
+// two-phase per matrix), several right-hand sides with every matrix
+// symmetric (fused only), several right-hand sides in general (fused or
+// two-phase per matrix).
+enum BatchAdjPath { kAdjSingle = 0, kAdjMrhsFused = 1, kAdjMrhsAny = 2 };
+
+template <typename VT, int L, int VX, bool IND, int PATH>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
@@ -69,12 +76,16 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
         A *gv = static_cast<A *>(d.gv);
         for (int32_t s = s0 + wave; s < s1; s += nw) {
             const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
-            if (nrhs == 1)
+            if constexpr (PATH == kAdjSingle) {
                 sr_adjoint<VT, L, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x, g, gx,
                                        gv, d.nnz, d.sym != 0, lds, lane, false);
-            else
+            } else if constexpr (PATH == kAdjMrhsFused) {
+                sr_adjoint_fused_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_src, vals, x, g, gx, gv,
+                                                      d.nnz, nrhs, lds, lane);
+            } else {
                 sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x,
                                                 g, gx, gv, d.nnz, nrhs, d.sym != 0, lds, lane);
+            }
         }
     }
 }
@@ -113,25 +124,64 @@ hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems
     });
 }
 
+// The adjoint path for a launch: several right-hand sides over symmetric
+// patterns with both outputs and FP32 accumulation take the fused-only
+// instantiation.
+inline int adj_path(csrk_dtype store, int nrhs, bool all_sym, bool both) {
+    if (nrhs == 1) return kAdjSingle;
+    return (all_sym && both && store != CSRK_F64) ? kAdjMrhsFused : kAdjMrhsAny;
+}
+
+// Instantiations that a launch can choose: one right-hand side runs with one
+// column per lane, and the fused multi-column path stages 4-byte values
+// (FP32 accumulation) only.
+template <typename VT, int VX, int PATH>
+constexpr bool adj_variant_exists() {
+    if constexpr (PATH == kAdjSingle) return VX == 1;
+    if constexpr (PATH == kAdjMrhsFused) return sizeof(typename Store<VT>::A) == 4;
+    return true;
+}
+
+// Calls f(integral_constant<bool, IND>, integral_constant<int, PATH>).
+template <typename F>
+hipError_t by_adj_variant(bool ind, int path, F &&f) {
+    auto with_path = [&](auto ic) -> hipError_t {
+        switch (path) {
+        case kAdjSingle:
+            return f(ic, std::integral_constant<int, kAdjSingle>{});
+        case kAdjMrhsFused:
+            return f(ic, std::integral_constant<int, kAdjMrhsFused>{});
+        default:
+            return f(ic, std::integral_constant<int, kAdjMrhsAny>{});
+        }
+    };
+    return ind ? with_path(std::true_type{}) : with_path(std::false_type{});
+}
+
 hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, bool vec, hipStream_t st) {
+                         Shape s, int grid, bool ind, bool vec, bool all_sym, bool both, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
     const size_t lds = size_t(s.waves) * kBatchLds;
+    const int path = adj_path(store, nrhs, all_sym, both);
     return by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
         constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
-        if (ind)
-            hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, true>), dim3(grid), dim3(block), lds, st, descs, items,
-                               nitems, nrhs);
-        else
-            hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, false>), dim3(grid), dim3(block), lds, st, descs, items,
-                               nitems, nrhs);
-        return hipGetLastError();
+        return by_adj_variant(ind, path, [&](auto ic, auto pc) -> hipError_t {
+            constexpr bool IND = decltype(ic)::value;
+            constexpr int PATH = decltype(pc)::value;
+            if constexpr (!adj_variant_exists<VT, VX, PATH>()) {
+                return hipErrorInvalidValue;  // never chosen (see adj_variant_exists)
+            } else {
+                hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, IND, PATH>), dim3(grid), dim3(block), lds, st, descs,
+                                   items, nitems, nrhs);
+                return hipGetLastError();
+            }
+        });
     });
 }
 
-int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj, bool ind, bool vec) {
+int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj, bool ind, bool vec, bool all_sym, bool both) {
     int blocks = 1;
     const int block = s.waves * kWave;
     const hipError_t e = by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
@@ -139,10 +189,16 @@ int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj, bool ind, boo
         constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
         if (adj) {
             const size_t lds = size_t(s.waves) * kBatchLds;
-            return ind ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, VX, true>,
-                                                                      block, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_adjoint<VT, LL, VX, false>,
-                                                                      block, lds);
+            return by_adj_variant(ind, adj_path(store, nrhs, all_sym, both), [&](auto ic, auto pc) -> hipError_t {
+                constexpr bool IND = decltype(ic)::value;
+                constexpr int PATH = decltype(pc)::value;
+                if constexpr (!adj_variant_exists<VT, VX, PATH>())
+                    return hipErrorInvalidValue;
+                else
+                    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks,
+                                                                        k_batch_adjoint<VT, LL, VX, IND, PATH>, block,
+                                                                        lds);
+            });
         }
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, VX>, block,
                                                             size_t(s.waves) * batch_forward_lds<VT>(nrhs));

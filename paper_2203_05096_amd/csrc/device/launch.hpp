@@ -107,11 +107,15 @@ hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems
                          Shape s, int grid, bool vec, hipStream_t st);
 // `ind`: the descriptors' vals are caller values in CSR-k order (reached
 // through t_src); otherwise they are the handles' transposed copies.
+// `all_sym`: every matrix of the batch has a symmetric pattern; `both`: both
+// gradients are wanted (then a multi-right-hand-side launch with FP32
+// accumulation runs the fused-only kernel).
 hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, bool vec, hipStream_t st);
+                         Shape s, int grid, bool ind, bool vec, bool all_sym, bool both, hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
-int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec);
+int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec, bool all_sym,
+                    bool both);
 
 // Bandwidth probes (device/util.hip): a streaming read of `bytes` (a multiple of
 // 16, 16-byte aligned) writing one word per workgroup to part[0 .. probe_grid()),
