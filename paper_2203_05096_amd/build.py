@@ -43,9 +43,27 @@ def _obj(src):
     return os.path.join(BUILD_DIR, src.replace("/", "_") + ".o")
 
 
+def _source_digest() -> str:
+    """Digest of every source and header the library is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for base, _, files in sorted(os.walk(d)):
+            for f in sorted(files):
+                if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+                    p = os.path.join(base, f)
+                    h.update(p.encode())
+                    h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
     os.makedirs(OUT_DIR, exist_ok=True)
+    # hipcc compiles each file twice (device, then host) and reads the sources
+    # each time: a source edited during the build would leave objects (and the
+    # two halves of one object) from different versions.  Refuse that build.
+    before = _source_digest()
     jobs = []
     for s in HOST_SOURCES:
         jobs.append([CXX, *HOST_FLAGS, "-c", os.path.join(CSRC, s), "-o", _obj(s)])
@@ -55,6 +73,8 @@ def build(verbose: bool = False) -> str:
         for r in ex.map(_run, jobs):
             if verbose and (r.stdout or r.stderr):
                 print(r.stdout + r.stderr, file=sys.stderr)
+    if _source_digest() != before:
+        raise RuntimeError("sources changed while the library was being built; build again")
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp,
           *[_obj(s) for s in HOST_SOURCES + HIP_SOURCES], "-lgomp"])

@@ -40,6 +40,8 @@ struct csrk_matrix {
     // rows of A' / A'^T longer than csrk::dev::kLongRow (t_ only if nonsymmetric)
     std::vector<int32_t> long_rows, t_long_rows;
     int32_t *d_long = nullptr, *d_t_long = nullptr;
+    csrk::dev::SrRec *d_srec = nullptr;  // super-row records (see csrk::dev::SrRec)
+    int32_t srec_stride = 0;
     csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
     bool values_symmetric = false;  // A' == A'^T exactly: d_vals_t aliases d_vals
     int32_t max_row_any = 0;        // longest row of A' or of A'^T
@@ -51,6 +53,8 @@ struct csrk_batch_s {
     int device = -1;
     int32_t nitems = 0, max_n = 0;
     int2 *d_items = nullptr;
+    csrk::dev::SrRec *d_brec = nullptr;  // per item, brec_stride super-row records of its SSR
+    int32_t brec_stride = 1;
     // Descriptor tables on the device (forward, adjoint) and the host copies
     // they were written from; a call re-uploads only when its pointers change.
     csrk::dev::MatDesc *d_descs[2] = {nullptr, nullptr};
@@ -111,11 +115,13 @@ void free_device(csrk_matrix *h) {
     DeviceScope ds(h->device);
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
                     (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
-                    h->d_vals_t == h->d_vals ? nullptr : h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long})
+                    h->d_vals_t == h->d_vals ? nullptr : h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long,
+                    (void *)h->d_srec})
         if (p) (void)hipFree(p);
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
     h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
     h->d_long = h->d_t_long = nullptr;
+    h->d_srec = nullptr;
     h->d_vals = h->d_vals_t = nullptr;
     h->on_device = false;
 }
@@ -225,6 +231,8 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.split_fwd = h->split_fwd;
     a.split_adj = h->split_adj;
     a.max_row = h->max_row_any;
+    a.srec = h->d_srec;
+    a.srec_stride = h->srec_stride;
     return a;
 }
 
@@ -441,6 +449,21 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
             }
             h->long_rows = long_rows_of(h->row_ptr);
             h->t_long_rows = h->trans.symmetric ? std::vector<int32_t>() : long_rows_of(h->trans.t_row_ptr);
+            {
+                // one record per (SSR, slot): the slot-th super-row's rows and entries
+                const size_t nssr = h->ssr_ptr.size() - 1;
+                int32_t stride = 1;
+                for (size_t t = 0; t < nssr; ++t) stride = std::max(stride, h->ssr_ptr[t + 1] - h->ssr_ptr[t]);
+                std::vector<csrk::dev::SrRec> rec(nssr * size_t(stride), csrk::dev::SrRec{0, 0, 0, 0});
+                for (size_t t = 0; t < nssr; ++t)
+                    for (int32_t s = h->ssr_ptr[t]; s < h->ssr_ptr[t + 1]; ++s) {
+                        const int32_t r0 = h->sr_ptr[size_t(s)], r1 = h->sr_ptr[size_t(s) + 1];
+                        rec[t * size_t(stride) + size_t(s - h->ssr_ptr[t])] =
+                            csrk::dev::SrRec{r0, r1, h->row_ptr[size_t(r0)], h->row_ptr[size_t(r1)]};
+                    }
+                h->srec_stride = stride;
+                h->d_srec = upload_array(rec, "super-row records");
+            }
             if (!h->long_rows.empty()) h->d_long = upload_array(h->long_rows, "long rows");
             if (!h->t_long_rows.empty()) h->d_t_long = upload_array(h->t_long_rows, "transposed long rows");
             h->split_fwd = xcd_split(h, h->row_ptr, nullptr);
@@ -856,6 +879,19 @@ csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_ba
             if (items.size() > size_t(INT32_MAX)) throw Error{CSRK_ERR_ARG, "work list too long"};
             bt->nitems = static_cast<int32_t>(items.size());
             bt->d_items = upload_array(items, "batch work list");
+            // super-row records per item (the same records each handle keeps)
+            for (int32_t b = 0; b < count; ++b) bt->brec_stride = std::max(bt->brec_stride, handles[b]->srec_stride);
+            std::vector<csrk::dev::SrRec> brec(items.size() * size_t(bt->brec_stride), csrk::dev::SrRec{0, 0, 0, 0});
+            for (size_t it = 0; it < items.size(); ++it) {
+                const csrk_matrix *h = handles[items[it].x];
+                const int32_t t = items[it].y;
+                for (int32_t s = h->ssr_ptr[size_t(t)]; s < h->ssr_ptr[size_t(t) + 1]; ++s) {
+                    const int32_t r0 = h->sr_ptr[size_t(s)], r1 = h->sr_ptr[size_t(s) + 1];
+                    brec[it * size_t(bt->brec_stride) + size_t(s - h->ssr_ptr[size_t(t)])] =
+                        csrk::dev::SrRec{r0, r1, h->row_ptr[size_t(r0)], h->row_ptr[size_t(r1)]};
+                }
+            }
+            bt->d_brec = upload_array(brec, "batch super-row records");
             for (int k = 0; k < 2; ++k)
                 hip_check(hipMalloc(&bt->d_descs[k], sizeof(csrk::dev::MatDesc) * size_t(count)), "batch descriptors");
             // Batch-wide kernel shape: the first handle's lanes/waves, which
@@ -866,6 +902,7 @@ csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_ba
             bt->cus = cus;
         } catch (...) {
             if (bt->d_items) (void)hipFree(bt->d_items);
+            if (bt->d_brec) (void)hipFree(bt->d_brec);
             for (auto *p : bt->d_descs)
                 if (p) (void)hipFree(p);
             delete bt;
@@ -965,7 +1002,8 @@ csrk_status csrk_batch_spmv(csrk_batch b, const void *const *vals, const void *c
         hipStream_t st = static_cast<hipStream_t>(stream);
         csrk::dev::MatDesc *descs = upload_descs(b, 0, vals, x, y, nullptr, nullptr, nullptr, st);
         const bool vec = all_aligned16({x, reinterpret_cast<const void *const *>(y)}, b->handles.size());
-        hip_check(csrk::dev::batch_forward(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
+        hip_check(csrk::dev::batch_forward(descs, b->d_items, b->d_brec, b->brec_stride, b->nitems, b->store, nrhs,
+                                           b->shape,
                                            batch_grid(b, nrhs, false, false, vec, false), vec, st),
                   "csrk_batch_spmv launch");
         return CSRK_OK;
@@ -989,7 +1027,8 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         const bool ind = vals && std::any_of(vals, vals + b->handles.size(), [](const void *p) { return p != nullptr; });
         const bool vec = all_aligned16({x, g, reinterpret_cast<const void *const *>(grad_x)}, b->handles.size());
         const bool both = grad_x && grad_vals;
-        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->nitems, b->store, nrhs, b->shape,
+        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->d_brec, b->brec_stride, b->nitems, b->store, nrhs,
+                                           b->shape,
                                            batch_grid(b, nrhs, true, ind, vec, both), ind, vec, b->all_sym, both, st),
                   "csrk_batch_spmv_adjoint launch");
         return CSRK_OK;
@@ -1033,6 +1072,7 @@ csrk_status csrk_batch_destroy(csrk_batch b) {
         if (!b) return CSRK_OK;
         DeviceScope ds(b->device);
         if (b->d_items) (void)hipFree(b->d_items);
+        if (b->d_brec) (void)hipFree(b->d_brec);
         for (auto *p : b->d_descs)
             if (p) (void)hipFree(p);
         delete b;

@@ -8,7 +8,7 @@ namespace dev {
 namespace {
 
 template <typename VT, int L, bool IND, bool FUSED, bool ADAPT>
-__global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
+__global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__ srec, int32_t stride,
                                                        const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ cols,
                                                        const int32_t *__restrict__ t_row_ptr,
@@ -35,14 +35,16 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
     unsigned char *lds = smem + size_t(wave) * kAdjointLds;
     const int32_t t = ssr_of_block(split, bid - long_blocks);
     if (t < 0) return;
-    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
     // one instantiation per path keeps the other path's registers out of it
     using A = typename Store<VT>::A;
-    for (int32_t s = s0 + wave; s < s1; s += nw) {
-        const int32_t r0 = uniform(sr_ptr[s]), r1 = uniform(sr_ptr[s + 1]);
+    // the SSR's super-rows from its records (slots past its last SR are empty)
+    for (int32_t w = wave; w < stride; w += nw) {
+        const SrRec rec = srec[int64_t(t) * stride + w];
+        if (rec.r0 >= rec.r1) break;
+        const int32_t r0 = rec.r0, r1 = rec.r1;
         if constexpr (FUSED) {
-            sr_adjoint_fused<VT, L, IND, ADAPT>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
-                                                true);
+            sr_adjoint_fused_rec<VT, L, IND, ADAPT>(rec, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
+                                                    true);
         } else {
             if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
             if (gx)
@@ -54,7 +56,7 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const int32_t *__restrict
 
 template <typename VT, int RL, int VX, bool IND>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
-    const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr, const int32_t *__restrict__ row_ptr,
+    const SrRec *__restrict__ srec, int32_t stride, const int32_t *__restrict__ row_ptr,
     const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr, const int32_t *__restrict__ t_col,
     const int32_t *__restrict__ t_src, const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
     const typename Store<VT>::X *__restrict__ g, typename Store<VT>::X *__restrict__ gx,
@@ -66,10 +68,19 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     unsigned char *lds = smem + size_t(wave) * kMrhsLds;
     const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
-    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-    for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_adjoint_mrhs<VT, RL, VX, IND>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, t_row_ptr, t_col,
-                                         t_src, valsT, x, g, gx, gv, nnz, nrhs, sym != 0, lds, lane);
+    for (int32_t w = wave; w < stride; w += nw) {
+        const SrRec rec = srec[int64_t(t) * stride + w];
+        if (rec.r0 >= rec.r1) break;
+        if constexpr (sizeof(typename Store<VT>::A) == 4) {
+            if (sym != 0 && gx && gv) {
+                sr_adjoint_fused_mrhs_rec<VT, RL, VX, IND>(rec, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, nrhs,
+                                                           lds, lane);
+                continue;
+            }
+        }
+        sr_adjoint_mrhs<VT, RL, VX, IND>(rec.r0, rec.r1, row_ptr, cols, t_row_ptr, t_col, t_src, valsT, x, g, gx, gv,
+                                         nnz, nrhs, sym != 0, lds, lane);
+    }
 }
 
 }  // namespace
@@ -103,7 +114,7 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                         by_adapt<LL>(adapt_windows(a, LL), [&](auto ac) {
                             hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F, decltype(ac)::value>),
                                                dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
-                                               size_t(s.waves) * kAdjointLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                               size_t(s.waves) * kAdjointLds, st, a.srec, a.srec_stride, a.row_ptr,
                                                a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
                                                static_cast<const X *>(x), static_cast<const X *>(g),
                                                static_cast<X *>(gx), static_cast<A *>(gv), a.nnz, int(a.sym),
@@ -123,7 +134,7 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                 return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                     constexpr int RL = decltype(rc)::value;
                     hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.split_adj.width * kXcds),
-                                       dim3(block), size_t(s.waves) * kMrhsLds, st, a.ssr_ptr, a.sr_ptr, a.row_ptr,
+                                       dim3(block), size_t(s.waves) * kMrhsLds, st, a.srec, a.srec_stride, a.row_ptr,
                                        a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
                                        static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
                                        nrhs, int(a.sym), a.split_adj);

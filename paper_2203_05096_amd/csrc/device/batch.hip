@@ -15,6 +15,7 @@ namespace {
 // (single right-hand side) or per row group (several: L lanes x VX columns).
 template <typename VT, int L, int VX>
 __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
+                                                        const SrRec *__restrict__ brec, int32_t stride,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
@@ -29,18 +30,19 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
     for (int32_t it = i0; it < i1; ++it) {
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
-        const int32_t s0 = d.ssr_ptr[item.y], s1 = d.ssr_ptr[item.y + 1];
         const VT *vals = static_cast<const VT *>(d.vals);
         const X *x = static_cast<const X *>(d.x);
         X *y = static_cast<X *>(d.y);
-        for (int32_t s = s0 + wave; s < s1; s += nw) {
-            const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
+        // the item's super-rows from its records (slots past its last SR are empty)
+        for (int32_t w = wave; w < stride; w += nw) {
+            const SrRec rec = brec[int64_t(it) * stride + w];
+            if (rec.r0 >= rec.r1) break;
             if (nrhs == 1)
-                sr_forward<VT, L, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz,
-                                         reinterpret_cast<A *>(lds) + kStagePad, lane, false);
+                sr_forward_rec<VT, L, false>(rec, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz,
+                                             reinterpret_cast<A *>(lds) + kStagePad, lane, false);
             else
-                sr_forward_mrhs<VT, L, VX, false>(r0, r1, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
-                                                  lane);
+                sr_forward_mrhs_rec<VT, L, VX, false>(rec, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
+                                                      lane);
         }
     }
 }
@@ -54,6 +56,7 @@ enum BatchAdjPath { kAdjSingle = 0, kAdjMrhsFused = 1, kAdjMrhsAny = 2 };
 
 template <typename VT, int L, int VX, bool IND, int PATH>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
+                                                        const SrRec *__restrict__ brec, int32_t stride,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
@@ -68,20 +71,22 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
     for (int32_t it = i0; it < i1; ++it) {
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
-        const int32_t s0 = d.ssr_ptr[item.y], s1 = d.ssr_ptr[item.y + 1];
         const VT *vals = static_cast<const VT *>(d.vals);
         const X *x = static_cast<const X *>(d.x);
         const X *g = static_cast<const X *>(d.g);
         X *gx = static_cast<X *>(d.gx);
         A *gv = static_cast<A *>(d.gv);
-        for (int32_t s = s0 + wave; s < s1; s += nw) {
-            const int32_t r0 = uniform(d.sr_ptr[s]), r1 = uniform(d.sr_ptr[s + 1]);
+        // the item's super-rows from its records (slots past its last SR are empty)
+        for (int32_t w = wave; w < stride; w += nw) {
+            const SrRec rec = brec[int64_t(it) * stride + w];
+            if (rec.r0 >= rec.r1) break;
+            const int32_t r0 = rec.r0, r1 = rec.r1;
             if constexpr (PATH == kAdjSingle) {
                 sr_adjoint<VT, L, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x, g, gx,
                                        gv, d.nnz, d.sym != 0, lds, lane, false);
             } else if constexpr (PATH == kAdjMrhsFused) {
-                sr_adjoint_fused_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_src, vals, x, g, gx, gv,
-                                                      d.nnz, nrhs, lds, lane);
+                sr_adjoint_fused_mrhs_rec<VT, L, VX, IND>(rec, d.row_ptr, d.col_idx, d.t_src, vals, x, g, gx, gv,
+                                                          d.nnz, nrhs, lds, lane);
             } else {
                 sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x,
                                                 g, gx, gv, d.nnz, nrhs, d.sym != 0, lds, lane);
@@ -111,15 +116,16 @@ hipError_t by_batch_shape(csrk_dtype store, int nrhs, const Shape &s, bool vec, 
 
 }  // namespace
 
-hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool vec, hipStream_t st) {
+hipError_t batch_forward(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
+                         csrk_dtype store, int nrhs, Shape s, int grid, bool vec, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
     return by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
         constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
         hipLaunchKernelGGL((k_batch_forward<VT, LL, VX>), dim3(grid), dim3(block),
-                           size_t(s.waves) * batch_forward_lds<VT>(nrhs), st, descs, items, nitems, nrhs);
+                           size_t(s.waves) * batch_forward_lds<VT>(nrhs), st, descs, items, brec, stride, nitems,
+                           nrhs);
         return hipGetLastError();
     });
 }
@@ -158,8 +164,9 @@ hipError_t by_adj_variant(bool ind, int path, F &&f) {
     return ind ? with_path(std::true_type{}) : with_path(std::false_type{});
 }
 
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, bool vec, bool all_sym, bool both, hipStream_t st) {
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
+                         csrk_dtype store, int nrhs, Shape s, int grid, bool ind, bool vec, bool all_sym, bool both,
+                         hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
     const size_t lds = size_t(s.waves) * kBatchLds;
@@ -174,7 +181,7 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems
                 return hipErrorInvalidValue;  // never chosen (see adj_variant_exists)
             } else {
                 hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, IND, PATH>), dim3(grid), dim3(block), lds, st, descs,
-                                   items, nitems, nrhs);
+                                   items, brec, stride, nitems, nrhs);
                 return hipGetLastError();
             }
         });

@@ -477,6 +477,66 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
     }
 }
 
+// y for the rows of one super-row given by its record.  When the whole
+// super-row fits one window (the common case), its stream and its row ends
+// are requested together straight from the record, instead of after reading
+// sr_ptr and then row_ptr: a workgroup's first loads then depend on one load
+// (the record) rather than three.  Otherwise sr_forward walks it in windows.
+// Results are bit for bit those of sr_forward.
+template <typename VT, int L, bool IND, bool ADAPT = false, bool DOT = false>
+__device__ __forceinline__ void sr_forward_rec(const SrRec &rec, const int32_t *__restrict__ row_ptr,
+                                               const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                               const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
+                                               typename Store<VT>::X *__restrict__ y, int64_t nnz,
+                                               typename Store<VT>::A *__restrict__ buf, int lane, bool skip_long,
+                                               const double *__restrict__ pdot = nullptr, double *dot = nullptr) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    constexpr int V = Store<VT>::V;
+    constexpr int U = kStageEntries / (kWave * V);
+    constexpr int WIN = kStageEntries - V;
+    const int32_t r0 = rec.r0, r1 = rec.r1, cs = rec.e0, ce = rec.e1;
+    const int nrows = r1 - r0;
+    if (nrows > kWave || ce - cs > WIN) {
+        sr_forward<VT, L, IND, ADAPT, DOT>(r0, r1, row_ptr, cols, src, vals, x, y, nnz, buf, lane, skip_long, pdot,
+                                           dot);
+        return;
+    }
+    const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+    A v[U][V];
+    int32_t c[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * V;
+        if (pos < ce) {
+            load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                v[u][e] = A(0);
+                c[u][e] = 0;
+            }
+        }
+    }
+    const int32_t my_end = lane < nrows ? row_ptr[r0 + lane + 1] : 0;
+    A xv[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) xv[u][e] = A(x[c[u][e]]);
+    const int32_t off0 = int32_t(base - cs);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) buf[off0 + u * kWave * V + e] = v[u][e] * xv[u][e];
+    wave_lds_sync();
+    window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) {
+        y[r0 + rr] = X(acc);
+        if constexpr (DOT) *dot += double(X(acc)) * pdot[r0 + rr];
+    });
+    wave_lds_sync();
+}
+
 // ------------------------------------------------------------------ rows longer than kLongRow
 //
 // The main kernels leave rows longer than kLongRow to blocks of their own in
@@ -610,12 +670,105 @@ __device__ __forceinline__ T slice_sum(T v) {
     return v;
 }
 
-// y for rows r0..r1-1 with nrhs right-hand sides (row-major n x nrhs).  Per
-// window of whole rows, the (value, column) pairs are streamed into LDS with
-// 16-byte loads; then RL lanes per row each accumulate VX consecutive columns,
-// gathering VX-wide slices of the x rows (64/RL rows per pass).  Values are
-// vals[k] or vals[src[k]] (IND).  VX > 1 requires nrhs % VX == 0 and 16-byte
-// aligned x / y.
+// One window of the multi-right-hand-side product: rows [ra, ra + nrows)
+// with entries [cs, ce) (lane i holds the end of row ra + i in my_end).  The
+// (value, column) pairs are streamed into LDS with 16-byte loads, staged at
+// their offset from the window's 16-byte-aligned start so that each lane's
+// step is one aligned LDS write; then RL lanes per row each accumulate VX
+// consecutive columns, gathering VX-wide slices of the x rows (64/RL rows per
+// pass).  Returns after a closing wavefront sync (the LDS may be reused).
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void mrhs_forward_window(int32_t ra, int nrows, int32_t cs, int32_t ce, int32_t my_end,
+                                                    const int32_t *__restrict__ cols,
+                                                    const int32_t *__restrict__ src, const VT *__restrict__ vals,
+                                                    const typename Store<VT>::X *__restrict__ x,
+                                                    typename Store<VT>::X *__restrict__ y, int64_t nnz, int nrhs,
+                                                    unsigned char *__restrict__ lds, int lane) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * V);
+    constexpr int RPP = kWave / RL;  // rows per pass
+    constexpr int CPP = RL * VX;     // columns per pass
+    A *sval = reinterpret_cast<A *>(lds);
+    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
+    const int q = lane % RL;
+    const int rsub = lane / RL;
+    const int32_t cs0 = cs & ~(V - 1);
+    const int32_t off = cs - cs0;  // LDS index of entry cs
+    const int64_t base = int64_t(cs0) + int64_t(lane) * V;
+    A v[U][V];
+    int32_t c[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * V;
+        if (pos < ce) {
+            load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                v[u][e] = A(0);
+                c[u][e] = 0;
+            }
+        }
+    }
+    // aligned staging: the lane's V entries of step u at LDS index u*64*V + lane*V
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            sval[u * kWave * V + lane * V + e] = v[u][e];
+            scol[u * kWave * V + lane * V + e] = c[u][e];
+        }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int b = 0; b < nrows; b += RPP) {
+        const int rr = b + rsub;
+        const bool act = rr < nrows;
+        const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+        const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+        const int32_t rbeg = rr == 0 ? 0 : prev;
+        if (!act) continue;
+        for (int cb = 0; cb < nrhs; cb += CPP) {
+            const int col0 = cb + q * VX;
+            if (col0 >= nrhs) continue;
+            A acc[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) acc[e] = A(0);
+            // four entries at a time: their x slices are all requested before any is used
+            for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
+                X xv[4][VX];
+                A a[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = k0 + t < rend;
+                    a[t] = ok ? sval[off + k0 + t] : A(0);
+                    if (ok) {
+                        load_cols<X, VX>(x + int64_t(scol[off + k0 + t]) * nrhs + col0, xv[t]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) xv[t][e] = X(0);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) acc[e] += a[t] * A(xv[t][e]);
+            }
+            X out[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) out[e] = X(acc[e]);
+            store_cols<X, VX>(y + int64_t(ra + rr) * nrhs + col0, out);
+        }
+    }
+    wave_lds_sync();
+}
+
+// y for rows r0..r1-1 with nrhs right-hand sides (row-major n x nrhs), in
+// windows of whole rows (mrhs_forward_window).  Values are vals[k] or
+// vals[src[k]] (IND).  VX > 1 requires nrhs % VX == 0 and 16-byte aligned
+// x / y.
 template <typename VT, int RL, int VX, bool IND>
 __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
@@ -626,13 +779,9 @@ __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const in
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
-    constexpr int CAP = kStageEntries;
-    constexpr int U = CAP / (kWave * V);
-    constexpr int WIN = CAP - V;
+    constexpr int WIN = kStageEntries - V;
     constexpr int RPP = kWave / RL;  // rows per pass
     constexpr int CPP = RL * VX;     // columns per pass
-    A *sval = reinterpret_cast<A *>(lds);
-    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
     const int q = lane % RL;
     const int rsub = lane / RL;
     int32_t ra = r0;
@@ -672,78 +821,32 @@ __device__ __forceinline__ void sr_forward_mrhs(int32_t r0, int32_t r1, const in
         const int32_t ce = uniform(__shfl(my_end, nrows - 1));
         const int32_t nra = ra + nrows;
         const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
-        const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
-        A v[U][V];
-        int32_t c[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t pos = base + int64_t(u) * kWave * V;
-            if (pos < ce) {
-                load_vec<VT, IND>(vals, cols, src, pos, nnz, v[u], c[u]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    v[u][e] = A(0);
-                    c[u][e] = 0;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int64_t k = base + int64_t(u) * kWave * V + e;
-                if (k >= cs && k < ce) {
-                    sval[k - cs] = v[u][e];
-                    scol[k - cs] = c[u][e];
-                }
-            }
-        wave_lds_sync();
-#pragma unroll 1
-        for (int b = 0; b < nrows; b += RPP) {
-            const int rr = b + rsub;
-            const bool act = rr < nrows;
-            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
-            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
-            const int32_t rbeg = rr == 0 ? 0 : prev;
-            if (!act) continue;
-            for (int cb = 0; cb < nrhs; cb += CPP) {
-                const int col0 = cb + q * VX;
-                if (col0 >= nrhs) continue;
-                A acc[VX];
-#pragma unroll
-                for (int e = 0; e < VX; ++e) acc[e] = A(0);
-                // four entries at a time: their x slices are all requested before any is used
-                for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
-                    X xv[4][VX];
-                    A a[4];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const bool ok = k0 + t < rend;
-                        a[t] = ok ? sval[k0 + t] : A(0);
-                        if (ok) {
-                            load_cols<X, VX>(x + int64_t(scol[k0 + t]) * nrhs + col0, xv[t]);
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < VX; ++e) xv[t][e] = X(0);
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-#pragma unroll
-                        for (int e = 0; e < VX; ++e) acc[e] += a[t] * A(xv[t][e]);
-                }
-                X out[VX];
-#pragma unroll
-                for (int e = 0; e < VX; ++e) out[e] = X(acc[e]);
-                store_cols<X, VX>(y + int64_t(ra + rr) * nrhs + col0, out);
-            }
-        }
-        wave_lds_sync();
+        mrhs_forward_window<VT, RL, VX, IND>(ra, nrows, cs, ce, my_end, cols, src, vals, x, y, nnz, nrhs, lds, lane);
         cs = ce;
         ra = nra;
         my_end = next_end;
     }
+}
+
+// The multi-right-hand-side product of one super-row given by its record:
+// a super-row that fits one window is streamed straight from the record
+// (its stream and row ends requested together); otherwise sr_forward_mrhs.
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void sr_forward_mrhs_rec(const SrRec &rec, const int32_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                                    const VT *__restrict__ vals,
+                                                    const typename Store<VT>::X *__restrict__ x,
+                                                    typename Store<VT>::X *__restrict__ y, int64_t nnz, int nrhs,
+                                                    unsigned char *__restrict__ lds, int lane) {
+    constexpr int WIN = kStageEntries - Store<VT>::V;
+    const int nrows = rec.r1 - rec.r0;
+    if (nrows > kWave || rec.e1 - rec.e0 > WIN) {
+        sr_forward_mrhs<VT, RL, VX, IND>(rec.r0, rec.r1, row_ptr, cols, src, vals, x, y, nnz, nrhs, lds, lane);
+        return;
+    }
+    const int32_t my_end = lane < nrows ? row_ptr[rec.r0 + lane + 1] : 0;
+    mrhs_forward_window<VT, RL, VX, IND>(rec.r0, nrows, rec.e0, rec.e1, my_end, cols, src, vals, x, y, nnz, nrhs, lds,
+                                         lane);
 }
 
 
@@ -1129,6 +1232,129 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
     }
 }
 
+// Both gradients of one super-row of a symmetric pattern given by its record
+// (the fused adjoint).  When the whole super-row fits one window, its stream,
+// its row ends and the g of its rows are requested together straight from the
+// record; otherwise sr_adjoint_fused walks it in windows.  Results are bit for
+// bit those of sr_adjoint_fused.
+template <typename VT, int L, bool IND, bool ADAPT = false>
+__device__ __forceinline__ void sr_adjoint_fused_rec(const SrRec &rec, const int32_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ cols, const int32_t *__restrict__ src,
+                                                     const VT *__restrict__ valsT,
+                                                     const typename Store<VT>::X *__restrict__ x,
+                                                     const typename Store<VT>::X *__restrict__ g,
+                                                     typename Store<VT>::X *__restrict__ gx,
+                                                     typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                     unsigned char *__restrict__ lds, int lane, bool skip_long) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * V);
+    constexpr int WIN = CAP - V;
+    typedef A AV __attribute__((ext_vector_type(V)));
+    const int32_t r0 = rec.r0, r1 = rec.r1, cs = rec.e0, ce = rec.e1;
+    const int nrows = r1 - r0;
+    if (nrows > kWave || ce - cs > WIN) {
+        sr_adjoint_fused<VT, L, IND, ADAPT>(r0, r1, row_ptr, cols, src, valsT, x, g, gx, gv, nnz, lds, lane,
+                                            skip_long);
+        return;
+    }
+    A *buf = reinterpret_cast<A *>(lds) + kStagePad;
+    unsigned char *rowid = lds + kStageBytes;
+    A *gwin = reinterpret_cast<A *>(lds + kStageBytes + CAP);
+    const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+    A v[U][V];
+    int32_t c[U][V];
+    auto stream = [&]() {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t pos = base + int64_t(u) * kWave * V;
+            if (pos < ce) {
+                load_vec<VT, IND>(valsT, cols, src, pos, nnz, v[u], c[u]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    v[u][e] = A(0);
+                    c[u][e] = 0;
+                }
+            }
+        }
+    };
+    A xs[U][V], gs[U][V];
+    auto gathers = [&]() {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                xs[u][e] = (k >= cs && k < ce) ? A(x[c[u][e]]) : A(0);
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = base + int64_t(u) * kWave * V + e;
+                gs[u][e] = (k >= cs && k < ce) ? A(g[c[u][e]]) : A(0);
+            }
+    };
+    int32_t my_end = 0;
+    A gi = A(0);
+    auto row_map = [&]() {
+        const int32_t prev_end = __shfl(my_end, lane > 0 ? lane - 1 : 0);
+        if (lane < nrows) {
+            gwin[lane] = gi;
+            for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
+        }
+    };
+    // Order of the requests (measured): with 16-byte loads of 8 entries (BF16)
+    // the row ends come first and the row map is built while the stream is in
+    // flight; with 2 or 4 entries per load the stream comes first and the row
+    // map is built while the gathers are in flight (27-point 100^3 FP64
+    // adjoint 141 -> 120 us, BF16 111 -> 96 us for the better order).
+    if constexpr (V >= 8) {
+        my_end = lane < nrows ? row_ptr[r0 + lane + 1] : 0;
+        gi = lane < nrows ? A(g[r0 + lane]) : A(0);
+        stream();
+        row_map();
+        gathers();
+    } else {
+        stream();
+        my_end = lane < nrows ? row_ptr[r0 + lane + 1] : 0;
+        gi = lane < nrows ? A(g[r0 + lane]) : A(0);
+        gathers();
+        row_map();
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * V;
+        A gvv[V];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            const int64_t k = pos + e;
+            const bool ok = k >= cs && k < ce;
+            gvv[e] = ok ? gwin[rowid[k - cs]] * xs[u][e] : A(0);
+            if (ok) buf[k - cs] = v[u][e] * gs[u][e];
+        }
+        if (pos >= cs && pos + V <= ce) {
+            AV ov;
+#pragma unroll
+            for (int e = 0; e < V; ++e) ov[e] = gvv[e];
+            *reinterpret_cast<AV *>(gv + pos) = ov;
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                const int64_t k = pos + e;
+                if (k >= cs && k < ce) gv[k] = gvv[e];
+            }
+        }
+    }
+    wave_lds_sync();
+    window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { gx[r0 + rr] = X(acc); });
+    wave_lds_sync();
+}
+
 // Both gradients of one super-row, single right-hand side.  `valsT` holds the
 // transposed values (aligned with t_col) unless IND, in which case it holds the
 // caller's values in CSR-k order and each transposed value is vals[t_src[p]].
@@ -1150,6 +1376,139 @@ __device__ __forceinline__ void sr_adjoint(int32_t r0, int32_t r1, const int32_t
     if (gx)
         sr_forward<VT, L, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
                                reinterpret_cast<A *>(lds) + kStagePad, lane, skip_long);
+}
+
+// One window of the fused multi-right-hand-side adjoint (symmetric pattern):
+// rows [ra, ra + nrows) with entries [cs, ce), lane i holding the end of row
+// ra + i in my_end.  The (transposed value, column) pairs are staged in LDS at
+// their offset from the window's 16-byte-aligned start (one aligned write per
+// lane and step); then RL lanes per row, VX columns each, gather the x and g
+// slices of every entry j of row i, add a_ji g_j into grad_x[i] and sum
+// g_i . x_j over the columns into grad_vals (LDS, then 16-byte stores).
+// Ends with a wavefront sync.
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void mrhs_adjoint_fused_window(int32_t ra, int nrows, int32_t cs, int32_t ce,
+                                                          int32_t my_end, const int32_t *__restrict__ cols,
+                                                          const int32_t *__restrict__ src,
+                                                          const VT *__restrict__ valsT,
+                                                          const typename Store<VT>::X *__restrict__ x,
+                                                          const typename Store<VT>::X *__restrict__ g,
+                                                          typename Store<VT>::X *__restrict__ gx,
+                                                          typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                          int nrhs, unsigned char *__restrict__ lds, int lane) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * V);
+    constexpr int RPP = kWave / RL;
+    constexpr int CPP = RL * VX;
+    constexpr int VA = 16 / int(sizeof(A));
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    A *sval = reinterpret_cast<A *>(lds);
+    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
+    A *sgv = reinterpret_cast<A *>(lds + CAP * (sizeof(A) + sizeof(int32_t)));
+    const int q = lane % RL;
+    const int rsub = lane / RL;
+    const int32_t off = cs - (cs & ~(V - 1));  // LDS index of entry cs
+    const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+    A v[U][V];
+    int32_t c[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * V;
+        if (pos < ce) {
+            load_vec<VT, IND>(valsT, cols, src, pos, nnz, v[u], c[u]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) {
+                v[u][e] = A(0);
+                c[u][e] = 0;
+            }
+        }
+    }
+    // aligned staging: the lane's V entries of step u at LDS index u*64*V + lane*V
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+            sval[u * kWave * V + lane * V + e] = v[u][e];
+            scol[u * kWave * V + lane * V + e] = c[u][e];
+        }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int b = 0; b < nrows; b += RPP) {
+        const int rr = b + rsub;
+        const bool act = rr < nrows;
+        const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
+        const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
+        const int32_t rbeg = rr == 0 ? 0 : prev;
+        if (!act) continue;  // a row's RL lanes are active or idle together
+        for (int cb = 0; cb < nrhs; cb += CPP) {
+            const int col0 = cb + q * VX;
+            const bool cok = col0 < nrhs;
+            X gi[VX];
+            A acc[VX];
+#pragma unroll
+            for (int e = 0; e < VX; ++e) {
+                gi[e] = X(0);
+                acc[e] = A(0);
+            }
+            if (cok) load_cols<X, VX>(g + int64_t(ra + rr) * nrhs + col0, gi);
+            // four entries at a time: their x and g slices are all requested before any is used
+            for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
+                X xv[4][VX], gj[4][VX];
+                A a[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = cok && k0 + t < rend;
+                    a[t] = ok ? sval[off + k0 + t] : A(0);
+                    if (ok) {
+                        const int64_t j = scol[off + k0 + t];
+                        load_cols<X, VX>(x + j * nrhs + col0, xv[t]);
+                        load_cols<X, VX>(g + j * nrhs + col0, gj[t]);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VX; ++e) xv[t][e] = gj[t][e] = X(0);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    A p = 0;
+#pragma unroll
+                    for (int e = 0; e < VX; ++e) {
+                        p += A(gi[e]) * A(xv[t][e]);
+                        acc[e] += a[t] * A(gj[t][e]);
+                    }
+                    p = group_sum<RL>(p);
+                    if (q == 0 && k0 + t < rend) sgv[k0 + t] = cb == 0 ? p : sgv[k0 + t] + p;
+                }
+            }
+            if (cok) {
+                X out[VX];
+#pragma unroll
+                for (int e = 0; e < VX; ++e) out[e] = X(acc[e]);
+                store_cols<X, VX>(gx + int64_t(ra + rr) * nrhs + col0, out);
+            }
+        }
+    }
+    wave_lds_sync();
+    for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ce; pos += int64_t(kWave) * VA) {
+        if (pos >= cs && pos + VA <= ce) {
+            AV ov;
+#pragma unroll
+            for (int e = 0; e < VA; ++e) ov[e] = sgv[pos + e - cs];
+            *reinterpret_cast<AV *>(gv + pos) = ov;
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e) {
+                const int64_t k = pos + e;
+                if (k >= cs && k < ce) gv[k] = sgv[k - cs];
+            }
+        }
+    }
+    wave_lds_sync();
 }
 
 // Both gradients of one super-row of a symmetric pattern, several right-hand
@@ -1237,109 +1596,37 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs(int32_t r0, int32_t r1, co
         const int32_t ce = uniform(__shfl(my_end, nrows - 1));
         const int32_t nra = ra + nrows;
         const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
-        const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
-        A v[U][V];
-        int32_t c[U][V];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t pos = base + int64_t(u) * kWave * V;
-            if (pos < ce) {
-                load_vec<VT, IND>(valsT, cols, src, pos, nnz, v[u], c[u]);
-            } else {
-#pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    v[u][e] = A(0);
-                    c[u][e] = 0;
-                }
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int e = 0; e < V; ++e) {
-                const int64_t k = base + int64_t(u) * kWave * V + e;
-                if (k >= cs && k < ce) {
-                    sval[k - cs] = v[u][e];
-                    scol[k - cs] = c[u][e];
-                }
-            }
-        wave_lds_sync();
-#pragma unroll 1
-        for (int b = 0; b < nrows; b += RPP) {
-            const int rr = b + rsub;
-            const bool act = rr < nrows;
-            const int32_t rend = __shfl(my_end, act ? rr : 0) - cs;
-            const int32_t prev = __shfl(my_end, (act && rr > 0) ? rr - 1 : 0) - cs;
-            const int32_t rbeg = rr == 0 ? 0 : prev;
-            if (!act) continue;  // a row's RL lanes are active or idle together
-            for (int cb = 0; cb < nrhs; cb += CPP) {
-                const int col0 = cb + q * VX;
-                const bool cok = col0 < nrhs;
-                X gi[VX];
-                A acc[VX];
-#pragma unroll
-                for (int e = 0; e < VX; ++e) {
-                    gi[e] = X(0);
-                    acc[e] = A(0);
-                }
-                if (cok) load_cols<X, VX>(g + int64_t(ra + rr) * nrhs + col0, gi);
-                // four entries at a time: their x and g slices are all requested before any is used
-                for (int32_t k0 = rbeg; k0 < rend; k0 += 4) {
-                    X xv[4][VX], gj[4][VX];
-                    A a[4];
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const bool ok = cok && k0 + t < rend;
-                        a[t] = ok ? sval[k0 + t] : A(0);
-                        if (ok) {
-                            const int64_t j = scol[k0 + t];
-                            load_cols<X, VX>(x + j * nrhs + col0, xv[t]);
-                            load_cols<X, VX>(g + j * nrhs + col0, gj[t]);
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < VX; ++e) xv[t][e] = gj[t][e] = X(0);
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        A p = 0;
-#pragma unroll
-                        for (int e = 0; e < VX; ++e) {
-                            p += A(gi[e]) * A(xv[t][e]);
-                            acc[e] += a[t] * A(gj[t][e]);
-                        }
-                        p = group_sum<RL>(p);
-                        if (q == 0 && k0 + t < rend) sgv[k0 + t] = cb == 0 ? p : sgv[k0 + t] + p;
-                    }
-                }
-                if (cok) {
-                    X out[VX];
-#pragma unroll
-                    for (int e = 0; e < VX; ++e) out[e] = X(acc[e]);
-                    store_cols<X, VX>(gx + int64_t(ra + rr) * nrhs + col0, out);
-                }
-            }
-        }
-        wave_lds_sync();
-        for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ce; pos += int64_t(kWave) * VA) {
-            if (pos >= cs && pos + VA <= ce) {
-                AV ov;
-#pragma unroll
-                for (int e = 0; e < VA; ++e) ov[e] = sgv[pos + e - cs];
-                *reinterpret_cast<AV *>(gv + pos) = ov;
-            } else {
-#pragma unroll
-                for (int e = 0; e < VA; ++e) {
-                    const int64_t k = pos + e;
-                    if (k >= cs && k < ce) gv[k] = sgv[k - cs];
-                }
-            }
-        }
-        wave_lds_sync();
+        mrhs_adjoint_fused_window<VT, RL, VX, IND>(ra, nrows, cs, ce, my_end, cols, src, valsT, x, g, gx, gv, nnz,
+                                                   nrhs, lds, lane);
         cs = ce;
         ra = nra;
         my_end = next_end;
     }
+}
+
+// The fused multi-right-hand-side adjoint of one super-row given by its
+// record: a super-row that fits one window is streamed straight from the
+// record; otherwise sr_adjoint_fused_mrhs.
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void sr_adjoint_fused_mrhs_rec(const SrRec &rec, const int32_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ cols,
+                                                          const int32_t *__restrict__ src,
+                                                          const VT *__restrict__ valsT,
+                                                          const typename Store<VT>::X *__restrict__ x,
+                                                          const typename Store<VT>::X *__restrict__ g,
+                                                          typename Store<VT>::X *__restrict__ gx,
+                                                          typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
+                                                          unsigned char *__restrict__ lds, int lane) {
+    constexpr int WIN = kStageEntries - Store<VT>::V;
+    const int nrows = rec.r1 - rec.r0;
+    if (nrows > kWave || rec.e1 - rec.e0 > WIN) {
+        sr_adjoint_fused_mrhs<VT, RL, VX, IND>(rec.r0, rec.r1, row_ptr, cols, src, valsT, x, g, gx, gv, nnz, nrhs, lds,
+                                               lane);
+        return;
+    }
+    const int32_t my_end = lane < nrows ? row_ptr[rec.r0 + lane + 1] : 0;
+    mrhs_adjoint_fused_window<VT, RL, VX, IND>(rec.r0, nrows, rec.e0, rec.e1, my_end, cols, src, valsT, x, g, gx, gv,
+                                               nnz, nrhs, lds, lane);
 }
 
 // Both gradients of one super-row, several right-hand sides (RL lanes x VX

@@ -9,7 +9,7 @@ namespace dev {
 namespace {
 
 template <typename VT, int L, bool ADAPT>
-__global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ ssr_ptr, const int32_t *__restrict__ sr_ptr,
+__global__ void __launch_bounds__(1024) k_spmv_csrk(const SrRec *__restrict__ srec, int32_t stride,
                                                     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ cols,
                                                     const VT *__restrict__ vals, const typename Store<VT>::X *__restrict__ x,
                                                     typename Store<VT>::X *__restrict__ y, int64_t nnz,
@@ -28,10 +28,12 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
     A *buf = reinterpret_cast<A *>(smem + size_t(wave) * kStageBytes) + kStagePad;
     const int32_t t = ssr_of_block(split, bid - long_blocks);
     if (t < 0) return;
-    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-    for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward<VT, L, false, ADAPT>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals, x,
-                                        y, nnz, buf, lane, true);
+    // the SSR's super-rows from its records (slots past its last SR are empty)
+    for (int32_t w = wave; w < stride; w += nw) {
+        const SrRec rec = srec[int64_t(t) * stride + w];
+        if (rec.r0 >= rec.r1) break;
+        sr_forward_rec<VT, L, false, ADAPT>(rec, row_ptr, cols, nullptr, vals, x, y, nnz, buf, lane, true);
+    }
 }
 
 // The forward product y = A'x plus, per workgroup, the partial inner product
@@ -40,8 +42,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk(const int32_t *__restrict__ 
 // stores, in storage order; lanes, then wavefronts, are added in a fixed
 // order, so the partials do not depend on timing.  Used by CG for p . Ap.
 template <typename VT, int L>
-__global__ void __launch_bounds__(1024) k_spmv_csrk_dot(const int32_t *__restrict__ ssr_ptr,
-                                                        const int32_t *__restrict__ sr_ptr,
+__global__ void __launch_bounds__(1024) k_spmv_csrk_dot(const SrRec *__restrict__ srec, int32_t stride,
                                                         const int32_t *__restrict__ row_ptr,
                                                         const int32_t *__restrict__ cols, const VT *__restrict__ vals,
                                                         const typename Store<VT>::X *__restrict__ x,
@@ -64,10 +65,12 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_dot(const int32_t *__restric
         A *buf = reinterpret_cast<A *>(smem + size_t(wave) * kStageBytes) + kStagePad;
         const int32_t t = ssr_of_block(split, bid - long_blocks);
         if (t >= 0) {
-            const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-            for (int32_t s = s0 + wave; s < s1; s += nw)
-                sr_forward<VT, L, false, false, true>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols,
-                                                      nullptr, vals, x, y, nnz, buf, lane, true, pdot, &dot);
+            for (int32_t w = wave; w < stride; w += nw) {
+                const SrRec rec = srec[int64_t(t) * stride + w];
+                if (rec.r0 >= rec.r1) break;
+                sr_forward_rec<VT, L, false, false, true>(rec, row_ptr, cols, nullptr, vals, x, y, nnz, buf, lane, true,
+                                                          pdot, &dot);
+            }
         }
     }
 #pragma unroll
@@ -82,8 +85,7 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_dot(const int32_t *__restric
 }
 
 template <typename VT, int RL, int VX>
-__global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restrict__ ssr_ptr,
-                                                         const int32_t *__restrict__ sr_ptr,
+__global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const SrRec *__restrict__ srec, int32_t stride,
                                                          const int32_t *__restrict__ row_ptr,
                                                          const int32_t *__restrict__ cols, const VT *__restrict__ vals,
                                                          const typename Store<VT>::X *__restrict__ x,
@@ -96,10 +98,11 @@ __global__ void __launch_bounds__(1024) k_spmv_csrk_mrhs(const int32_t *__restri
     unsigned char *lds = smem + size_t(wave) * mrhs_forward_lds<VT>();
     const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
-    const int32_t s0 = ssr_ptr[t], s1 = ssr_ptr[t + 1];
-    for (int32_t s = s0 + wave; s < s1; s += nw)
-        sr_forward_mrhs<VT, RL, VX, false>(uniform(sr_ptr[s]), uniform(sr_ptr[s + 1]), row_ptr, cols, nullptr, vals,
-                                           x, y, nnz, nrhs, lds, lane);
+    for (int32_t w = wave; w < stride; w += nw) {
+        const SrRec rec = srec[int64_t(t) * stride + w];
+        if (rec.r0 >= rec.r1) break;
+        sr_forward_mrhs_rec<VT, RL, VX, false>(rec, row_ptr, cols, nullptr, vals, x, y, nnz, nrhs, lds, lane);
+    }
 }
 
 // ------------------------------------------------------------------ plain CSR baseline
@@ -156,9 +159,9 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
                 by_adapt<L>(adapt_windows(a, L), [&](auto ac) {
                     hipLaunchKernelGGL((k_spmv_csrk<VT, L, decltype(ac)::value>),
                                        dim3(long_blocks + a.split_fwd.width * kXcds), dim3(block),
-                                       size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
-                                       static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
-                                       a.nnz, a.long_rows, a.nlong, long_blocks, a.split_fwd);
+                                       size_t(s.waves) * kStageBytes, st, a.srec, a.srec_stride, a.row_ptr,
+                                       a.col_idx, static_cast<const VT *>(vals), static_cast<const X *>(x),
+                                       static_cast<X *>(y), a.nnz, a.long_rows, a.nlong, long_blocks, a.split_fwd);
                 });
                 return hipGetLastError();
             });
@@ -169,7 +172,8 @@ hipError_t spmv(const Arrays &a, csrk_dtype store, const void *vals, const void 
             return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                 constexpr int RL = decltype(rc)::value;
                 hipLaunchKernelGGL((k_spmv_csrk_mrhs<VT, RL, VX>), dim3(a.split_fwd.width * kXcds), dim3(block),
-                                   size_t(s.waves) * mrhs_forward_lds<VT>(), st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                                   size_t(s.waves) * mrhs_forward_lds<VT>(), st, a.srec, a.srec_stride, a.row_ptr,
+                                   a.col_idx,
                                    static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y),
                                    a.nnz, nrhs, a.split_fwd);
                 return hipGetLastError();
@@ -193,7 +197,7 @@ hipError_t spmv_dot(const Arrays &a, csrk_dtype store, const void *vals, const v
             constexpr int L = decltype(lc)::value;
             const int32_t long_blocks = (a.nlong + kXcds - 1) / kXcds * kXcds;
             hipLaunchKernelGGL((k_spmv_csrk_dot<VT, L>), dim3(spmv_grid(a)), dim3(block),
-                               size_t(s.waves) * kStageBytes, st, a.ssr_ptr, a.sr_ptr, a.row_ptr, a.col_idx,
+                               size_t(s.waves) * kStageBytes, st, a.srec, a.srec_stride, a.row_ptr, a.col_idx,
                                static_cast<const VT *>(vals), static_cast<const X *>(x), static_cast<X *>(y), a.nnz,
                                a.long_rows, a.nlong, long_blocks, a.split_fwd, pdot, part);
             return hipGetLastError();

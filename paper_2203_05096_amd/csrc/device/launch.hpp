@@ -27,6 +27,15 @@ struct XcdSplit {
     int32_t width = 0;  // largest range: the grid is width * kXcds blocks
 };
 
+// Bounds of one super-row: rows [r0, r1) and their entries [e0, e1).  The
+// handle keeps one record per (super-super-row, slot), slot w < stride holding
+// the SSR's w-th super-row (empty records, r0 == r1, pad short SSRs), so a
+// workgroup finds its super-rows' rows and entries with one load instead of
+// the chain ssr_ptr -> sr_ptr -> row_ptr.
+struct __attribute__((aligned(16))) SrRec {
+    int32_t r0, r1, e0, e1;
+};
+
 // Device arrays of one CSR-k matrix.
 struct Arrays {
     int32_t n = 0;
@@ -55,6 +64,8 @@ struct Arrays {
     XcdSplit split_fwd;  // by the forward's work (rows of A')
     XcdSplit split_adj;  // by the adjoint's work (rows of A' and of A'^T)
     int32_t max_row = 0;  // longest row of A' or of A'^T (nonzeros)
+    const SrRec *srec = nullptr;  // nssr * srec_stride super-row records
+    int32_t srec_stride = 0;      // most super-rows in one super-super-row
 };
 
 // Per-matrix record of a batched launch (device-resident table).
@@ -103,15 +114,17 @@ hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtyp
 
 // Batched launches: one grid over `nitems` (matrix, super-super-row) items.
 // `vec`: every right-hand-side block pointer is 16-byte aligned.
-hipError_t batch_forward(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool vec, hipStream_t st);
+// `brec`: per item, `stride` super-row records (SrRec) of its SSR.
+hipError_t batch_forward(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
+                         csrk_dtype store, int nrhs, Shape s, int grid, bool vec, hipStream_t st);
 // `ind`: the descriptors' vals are caller values in CSR-k order (reached
 // through t_src); otherwise they are the handles' transposed copies.
 // `all_sym`: every matrix of the batch has a symmetric pattern; `both`: both
 // gradients are wanted (then a multi-right-hand-side launch with FP32
 // accumulation runs the fused-only kernel).
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, int32_t nitems, csrk_dtype store, int nrhs,
-                         Shape s, int grid, bool ind, bool vec, bool all_sym, bool both, hipStream_t st);
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
+                         csrk_dtype store, int nrhs, Shape s, int grid, bool ind, bool vec, bool all_sym, bool both,
+                         hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec, bool all_sym,

@@ -131,15 +131,35 @@ def counters(args):
     lines += ["    " + c for c in args.command]
     lines += ["", f"Device source sha256: `{kernel_source_hash()}`", "", "Mean per dispatch:", "",
               "| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    kept = []
     for k in sorted(acc, key=lambda k: -len(next(iter(acc[k].values())))):
         if args.match and not any(m in k for m in args.match):
             continue
+        kept.append(k)
         n = max(len(v) for v in acc[k].values())
         cells = []
         for c in names:
             v = acc[k].get(c)
             cells.append(f"{sum(v) / len(v):.4g}" if v else "")
         lines.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+    # ratios that do not depend on the counters' units
+    mean = lambda k, c: sum(acc[k][c]) / len(acc[k][c]) if acc[k].get(c) else None  # noqa: E731
+    rows = []
+    for k in kept:
+        hit, miss = mean(k, "TCC_HIT_sum"), mean(k, "TCC_MISS_sum")
+        wait, alive = mean(k, "SQ_WAIT_ANY"), mean(k, "SQ_WAVE_CYCLES")
+        conf, lds = mean(k, "SQ_LDS_BANK_CONFLICT"), mean(k, "SQ_ACTIVE_INST_LDS")
+        cells = [f"{hit / (hit + miss):.2f}" if hit is not None and miss else "",
+                 f"{miss * 128 / 1e6:.0f}" if miss is not None else "",
+                 f"{wait / alive:.2f}" if wait is not None and alive else "",
+                 f"{conf / lds:.2f}" if conf is not None and lds else ""]
+        rows.append(f"| `{k}` | " + " | ".join(cells) + " |")
+    if rows:
+        lines += ["", "Ratios: L2 hit rate TCC_HIT / (TCC_HIT + TCC_MISS); L2 misses x 128 B (MB, the line size); "
+                      "share of wavefront time spent waiting SQ_WAIT_ANY / SQ_WAVE_CYCLES; LDS bank-conflict cycles "
+                      "per active LDS cycle.", "",
+                  "| kernel | L2 hit | L2 misses x 128 B (MB) | wait share | LDS conflicts / LDS active |",
+                  "|---|---|---|---|---|", *rows]
     print("\n".join(lines))
 
 
