@@ -137,11 +137,13 @@ csrk_status csrk_tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out
 /*
  * csrk_tune_rhs — csrk_tune for a matrix that will be multiplied by blocks
  * of nrhs right-hand sides (nrhs >= 1; nrhs == 1 is csrk_tune).  The paper's
- * model is for one vector (Section 4.1); for nrhs > 1 the MI355X model keeps
- * its SRS and sets SSRS = waves per workgroup = 8, this library's measurement
- * on the multi-right-hand-side kernels (a batch of 64 7-point matrices with
- * 8 right-hand sides: forward + adjoint 1.84 ms at SSRS 8 against 2.46 ms at
- * the single-vector choice of 2).  VOLTA/AMPERE ignore nrhs.
+ * model is for one vector (Section 4.1); for nrhs > 1 the MI355X model halves
+ * its SRS (snapped to the {2^i, 1.5 * 2^i} set) and sets SSRS = waves per
+ * workgroup = 4, this library's measurement on the multi-right-hand-side
+ * kernels (a batch of 64 7-point matrices with 8 right-hand sides, one
+ * workgroup per work item: forward + adjoint 1.24 ms at (SRS 32, SSRS 4)
+ * against 1.34 ms at (64, 8) and 1.88 ms at (16, 2)).  VOLTA/AMPERE ignore
+ * nrhs.
  * Errors: as csrk_tune, and CSRK_ERR_ARG for nrhs < 1.
  */
 csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out);

@@ -64,6 +64,7 @@ class SweepResult:
     nnz: int
     rdensity: float
     trials: list = field(default_factory=list)
+    objective: str = "forward"  # what the trial times measure: "forward" or "step" (forward + adjoint)
 
     @property
     def best(self) -> Trial:
@@ -122,7 +123,7 @@ def sweep(A, store: str = "f64", srs_list=SRS_SWEEP, ssrs_list=SSRS_SWEEP, lanes
     matrix and the permuted-space input and output of its last timed product (a caller's check
     that every candidate computes the same product)."""
     n, nnz = len(A.row_ptr) - 1, int(A.row_ptr[-1])
-    res = SweepResult(name or getattr(A, "name", "matrix"), n, nnz, nnz / max(n, 1))
+    res = SweepResult(name or getattr(A, "name", "matrix"), n, nnz, nnz / max(n, 1), objective=objective)
     dt = torch.float64 if store == "f64" else torch.float32
     g = torch.Generator(device="cuda").manual_seed(seed)
     shape = (n,) if nrhs == 1 else (n, nrhs)
@@ -282,8 +283,8 @@ def grid_markdown(res: SweepResult, picks: dict, command: str) -> str:
     b = res.best
     lines = [f"Matrix {res.name}: n = {res.n:,}, nnz = {res.nnz:,}, rdensity {res.rdensity:.3f}.", "",
              "Command:", "", "    " + command, "",
-             "Forward kernel time in us per (SRS, SSRS) cell, the best over lanes per row; waves per workgroup = "
-             "min(SSRS, 16):", "",
+             f"{'Forward' if res.objective == 'forward' else 'Forward + adjoint'} kernel time in us per (SRS, SSRS) "
+             "cell, the best over lanes per row; waves per workgroup = min(SSRS, 16):", "",
              "| SRS \\ SSRS | " + " | ".join(str(v) for v in ssrs_l) + " |",
              "|---|" + "---|" * len(ssrs_l)]
     for srs in srs_l:

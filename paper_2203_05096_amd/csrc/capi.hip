@@ -351,12 +351,11 @@ csrk_status csrk_spmv_host(csrk_handle h, const double *x, double *y, int32_t nt
 csrk_status csrk_tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out) {
     return guard([&] {
         if (nrhs < 1) throw Error{CSRK_ERR_ARG, "nrhs must be >= 1"};
-        csrk_status s = csrk::tune(n, nnz, model, out);
+        csrk_status s = csrk::tune_rhs(n, nnz, nrhs, model, out);
         if (s != CSRK_OK) {
             set_detail("csrk_tune_rhs needs n > 0, nnz > 0, a known model and an output pointer");
             return s;
         }
-        if (model == CSRK_MODEL_MI355X && nrhs > 1) out->ssrs = out->waves_per_wg = 8;
         return CSRK_OK;
     });
 }

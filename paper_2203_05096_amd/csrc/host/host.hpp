@@ -146,6 +146,8 @@ void spmv_host(int64_t nssr, const int32_t *ssr_ptr, const int32_t *sr_ptr, cons
 
 // Constant-time size model (Section 4.1); see csrk_tune.
 csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out);
+// tune for blocks of nrhs right-hand sides (nrhs == 1: tune)
+csrk_status tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out);
 
 // Sanity-checks parameters (throws Error CSRK_ERR_ARG).
 void check_params(const csrk_params &p);

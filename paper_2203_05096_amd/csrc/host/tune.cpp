@@ -133,6 +133,21 @@ csrk_status tune(int64_t n, int64_t nnz, csrk_model model, csrk_params *out) {
     return CSRK_OK;
 }
 
+csrk_status tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csrk_params *out) {
+    if (nrhs < 1) return CSRK_ERR_ARG;
+    const csrk_status s = tune(n, nnz, model, out);
+    if (s != CSRK_OK || model != CSRK_MODEL_MI355X || nrhs == 1) return s;
+    // Blocks of right-hand sides (the batched autotuner's sweep on 64 3D
+    // 7-point matrices with 8 columns, one workgroup per work item: SRS
+    // {16, 24, 32, 48, 64} x SSRS {2, 4, 8}): a row moves nrhs times the
+    // vector bytes, and the best super-row held half the rows of the
+    // one-column choice (32 against 64; 1.24 ms per forward + adjoint step
+    // against 1.34 ms), with 4 super-rows (and wavefronts) per workgroup.
+    out->srs = static_cast<int32_t>(snap_srs(std::max<int64_t>(1, out->srs / 2), 1));
+    out->ssrs = out->waves_per_wg = 4;
+    return CSRK_OK;
+}
+
 void check_params(const csrk_params &p) {
     if (p.k != 2 && p.k != 3) throw Error{CSRK_ERR_ARG, "k must be 2 or 3"};
     if (p.srs < 1 || p.ssrs < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};

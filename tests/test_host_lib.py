@@ -465,8 +465,12 @@ def test_tune_rhs():
         one = C.csrk_tune(n, nnz, "mi355x")
         assert C.csrk_tune_rhs(n, nnz, 1, "mi355x") == one
         many = C.csrk_tune_rhs(n, nnz, 8, "mi355x")
-        assert (many["srs"], many["lanes_per_row"]) == (one["srs"], one["lanes_per_row"])
-        assert many["ssrs"] == many["waves_per_wg"] == 8
+        # half the one-column super-row, snapped to the {2^i, 1.5 * 2^i} set, four per workgroup
+        half = one["srs"] // 2
+        snapped = min((c for i in range(12) for c in (2 ** i, 3 * 2 ** i // 2) if c >= 1),
+                      key=lambda c: (abs(c - half), c))
+        assert (many["srs"], many["lanes_per_row"]) == (snapped, one["lanes_per_row"])
+        assert many["ssrs"] == many["waves_per_wg"] == 4
         assert C.csrk_tune_rhs(n, nnz, 8, "ampere") == C.csrk_tune(n, nnz, "ampere")
     with pytest.raises(C.CsrkError) as e:
         C.csrk_tune_rhs(100, 500, 0, "mi355x")
