@@ -107,6 +107,24 @@ __device__ __forceinline__ T group_sum(T v) {
     return v;
 }
 
+// Products of one window staged in LDS at their offset from the window's
+// 16-byte-aligned start: lane l's V products of step u go to
+// buf[u * 64 * V + l * V ..], one aligned vector write per lane and step (no
+// bank conflicts between lanes), and entry k of a window starting at entry cs
+// sits at buf[k - (cs & ~(V - 1))].  Products of entries outside the window
+// land where no row sum reads.
+template <typename A, int U, int V>
+__device__ __forceinline__ void stage_products(A *__restrict__ buf, const A (&p)[U][V], int lane) {
+    typedef A PV __attribute__((ext_vector_type(V)));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        PV t;
+#pragma unroll
+        for (int e = 0; e < V; ++e) t[e] = p[u][e];
+        *reinterpret_cast<PV *>(buf + u * kWave * V + lane * V) = t;
+    }
+}
+
 // V consecutive column indices starting at pos (pos % V == 0) and the values
 // of those entries: vals[pos + e], or vals[src[pos + e]] when the values are
 // reached through an index map (IND).  Entries at or beyond nnz read as 0.
@@ -436,7 +454,6 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
         const int32_t nra = ra + nrows;
         const int32_t next_end = (nra + lane < r1) ? row_ptr[nra + lane + 1] : 0;
         const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
-        const int32_t off0 = int32_t(base - cs);  // window offset of this lane's first entry, >= -(V - 1)
         A v[U][V];
         int32_t c[U][V];
 #pragma unroll
@@ -461,12 +478,14 @@ __device__ __forceinline__ void sr_forward(int32_t r0, int32_t r1, const int32_t
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int e = 0; e < V; ++e) xv[u][e] = A(x[c[u][e]]);
+        A pr[U][V];
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
-            for (int e = 0; e < V; ++e) buf[off0 + u * kWave * V + e] = v[u][e] * xv[u][e];
+            for (int e = 0; e < V; ++e) pr[u][e] = v[u][e] * xv[u][e];
+        stage_products<A, U, V>(buf, pr, lane);
         wave_lds_sync();
-        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) {
+        window_row_sums<L, ADAPT>(buf + (cs - (cs & ~(V - 1))), nrows, my_end, cs, lane, [&](int rr, A acc) {
             y[ra + rr] = X(acc);
             if constexpr (DOT) *dot += double(X(acc)) * pdot[ra + rr];
         });
@@ -524,13 +543,14 @@ __device__ __forceinline__ void sr_forward_rec(const SrRec &rec, const int32_t *
     for (int u = 0; u < U; ++u)
 #pragma unroll
         for (int e = 0; e < V; ++e) xv[u][e] = A(x[c[u][e]]);
-    const int32_t off0 = int32_t(base - cs);
+    A pr[U][V];
 #pragma unroll
     for (int u = 0; u < U; ++u)
 #pragma unroll
-        for (int e = 0; e < V; ++e) buf[off0 + u * kWave * V + e] = v[u][e] * xv[u][e];
+        for (int e = 0; e < V; ++e) pr[u][e] = v[u][e] * xv[u][e];
+    stage_products<A, U, V>(buf, pr, lane);
     wave_lds_sync();
-    window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) {
+    window_row_sums<L, ADAPT>(buf + (cs - (cs & ~(V - 1))), nrows, my_end, cs, lane, [&](int rr, A acc) {
         y[r0 + rr] = X(acc);
         if constexpr (DOT) *dot += double(X(acc)) * pdot[r0 + rr];
     });
@@ -1197,6 +1217,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
                 gs[u][e] = (k >= cs && k < ce) ? A(g[c[u][e]]) : A(0);
             }
         wave_lds_sync();
+        A pr[U][V];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t pos = base + int64_t(u) * kWave * V;
@@ -1208,7 +1229,7 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
                 const A xj = xs[u][e];
                 const A gj = gs[u][e];
                 gvv[e] = ok ? gwin[rowid[k - cs]] * xj : A(0);
-                if (ok) buf[k - cs] = v[u][e] * gj;
+                pr[u][e] = v[u][e] * gj;
             }
             if (pos >= cs && pos + V <= ce) {
                 AV ov;
@@ -1223,8 +1244,10 @@ __device__ __forceinline__ void sr_adjoint_fused(int32_t r0, int32_t r1, const i
                 }
             }
         }
+        stage_products<A, U, V>(buf, pr, lane);
         wave_lds_sync();
-        window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { gx[ra + rr] = X(acc); });
+        window_row_sums<L, ADAPT>(buf + (cs - (cs & ~(V - 1))), nrows, my_end, cs, lane,
+                                  [&](int rr, A acc) { gx[ra + rr] = X(acc); });
         wave_lds_sync();
         cs = ce;
         ra = nra;
@@ -1326,6 +1349,7 @@ __device__ __forceinline__ void sr_adjoint_fused_rec(const SrRec &rec, const int
         row_map();
     }
     wave_lds_sync();
+    A pr[U][V];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t pos = base + int64_t(u) * kWave * V;
@@ -1335,7 +1359,7 @@ __device__ __forceinline__ void sr_adjoint_fused_rec(const SrRec &rec, const int
             const int64_t k = pos + e;
             const bool ok = k >= cs && k < ce;
             gvv[e] = ok ? gwin[rowid[k - cs]] * xs[u][e] : A(0);
-            if (ok) buf[k - cs] = v[u][e] * gs[u][e];
+            pr[u][e] = v[u][e] * gs[u][e];
         }
         if (pos >= cs && pos + V <= ce) {
             AV ov;
@@ -1350,8 +1374,10 @@ __device__ __forceinline__ void sr_adjoint_fused_rec(const SrRec &rec, const int
             }
         }
     }
+    stage_products<A, U, V>(buf, pr, lane);
     wave_lds_sync();
-    window_row_sums<L, ADAPT>(buf, nrows, my_end, cs, lane, [&](int rr, A acc) { gx[r0 + rr] = X(acc); });
+    window_row_sums<L, ADAPT>(buf + (cs - (cs & ~(V - 1))), nrows, my_end, cs, lane,
+                              [&](int rr, A acc) { gx[r0 + rr] = X(acc); });
     wave_lds_sync();
 }
 
