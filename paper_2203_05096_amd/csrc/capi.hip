@@ -40,7 +40,8 @@ struct csrk_matrix {
     // rows of A' / A'^T longer than csrk::dev::kLongRow (t_ only if nonsymmetric)
     std::vector<int32_t> long_rows, t_long_rows;
     int32_t *d_long = nullptr, *d_t_long = nullptr;
-    csrk::dev::SrRec *d_srec = nullptr;  // super-row records (see csrk::dev::SrRec)
+    csrk::dev::SrRec *d_srec = nullptr;    // super-row records (see csrk::dev::SrRec)
+    csrk::dev::SrRec *d_srec_t = nullptr;  // records of the same rows of A'^T (nonsymmetric patterns)
     int32_t srec_stride = 0;
     csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
     bool values_symmetric = false;  // A' == A'^T exactly: d_vals_t aliases d_vals
@@ -116,12 +117,12 @@ void free_device(csrk_matrix *h) {
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
                     (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
                     h->d_vals_t == h->d_vals ? nullptr : h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long,
-                    (void *)h->d_srec})
+                    (void *)h->d_srec, (void *)h->d_srec_t})
         if (p) (void)hipFree(p);
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
     h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
     h->d_long = h->d_t_long = nullptr;
-    h->d_srec = nullptr;
+    h->d_srec = h->d_srec_t = nullptr;
     h->d_vals = h->d_vals_t = nullptr;
     h->on_device = false;
 }
@@ -232,6 +233,7 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.split_adj = h->split_adj;
     a.max_row = h->max_row_any;
     a.srec = h->d_srec;
+    a.srec_t = sym ? h->d_srec : h->d_srec_t;
     a.srec_stride = h->srec_stride;
     return a;
 }
@@ -462,6 +464,15 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
                     }
                 h->srec_stride = stride;
                 h->d_srec = upload_array(rec, "super-row records");
+                if (!h->trans.symmetric) {
+                    // the same rows of A'^T: their entries in the transposed structure
+                    for (auto &r : rec)
+                        if (r.r0 < r.r1) {
+                            r.e0 = h->trans.t_row_ptr[size_t(r.r0)];
+                            r.e1 = h->trans.t_row_ptr[size_t(r.r1)];
+                        }
+                    h->d_srec_t = upload_array(rec, "transposed super-row records");
+                }
             }
             if (!h->long_rows.empty()) h->d_long = upload_array(h->long_rows, "long rows");
             if (!h->t_long_rows.empty()) h->d_t_long = upload_array(h->t_long_rows, "transposed long rows");

@@ -8,7 +8,8 @@ namespace dev {
 namespace {
 
 template <typename VT, int L, bool IND, bool FUSED, bool ADAPT>
-__global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__ srec, int32_t stride,
+__global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__ srec, const SrRec *__restrict__ srec_t,
+                                                       int32_t stride,
                                                        const int32_t *__restrict__ row_ptr,
                                                        const int32_t *__restrict__ cols,
                                                        const int32_t *__restrict__ t_row_ptr,
@@ -41,15 +42,16 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__
     for (int32_t w = wave; w < stride; w += nw) {
         const SrRec rec = srec[int64_t(t) * stride + w];
         if (rec.r0 >= rec.r1) break;
-        const int32_t r0 = rec.r0, r1 = rec.r1;
         if constexpr (FUSED) {
             sr_adjoint_fused_rec<VT, L, IND, ADAPT>(rec, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
                                                     true);
         } else {
-            if (gv) sr_grad_vals<VT>(r0, r1, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
+            // the same rows of A'^T (grad_x = their product with g)
+            const SrRec rect = srec_t[int64_t(t) * stride + w];
+            if (gv) sr_grad_vals_rec<VT>(rec, row_ptr, cols, x, g, gv, nnz, lds, lane, true);
             if (gx)
-                sr_forward<VT, L, IND, ADAPT>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
-                                              reinterpret_cast<A *>(lds) + kStagePad, lane, true);
+                sr_forward_rec<VT, L, IND, ADAPT>(rect, t_row_ptr, t_col, t_src, valsT, g, gx, nnz,
+                                                  reinterpret_cast<A *>(lds) + kStagePad, lane, true);
         }
     }
 }
@@ -114,7 +116,8 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                         by_adapt<LL>(adapt_windows(a, LL), [&](auto ac) {
                             hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F, decltype(ac)::value>),
                                                dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
-                                               size_t(s.waves) * kAdjointLds, st, a.srec, a.srec_stride, a.row_ptr,
+                                               size_t(s.waves) * kAdjointLds, st, a.srec, a.srec_t, a.srec_stride,
+                                               a.row_ptr,
                                                a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
                                                static_cast<const X *>(x), static_cast<const X *>(g),
                                                static_cast<X *>(gx), static_cast<A *>(gv), a.nnz, int(a.sym),

@@ -979,6 +979,88 @@ __device__ __forceinline__ void sr_grad_vals(int32_t r0, int32_t r1, const int32
     }
 }
 
+// grad_vals for the rows of one super-row given by its record.  When the
+// whole super-row fits one window, its column stream, row ends and the g of
+// its rows are requested together straight from the record (the row map is
+// built while the stream is in flight); otherwise sr_grad_vals walks it in
+// windows.  Results are bit for bit those of sr_grad_vals.
+template <typename VT>
+__device__ __forceinline__ void sr_grad_vals_rec(const SrRec &rec, const int32_t *__restrict__ row_ptr,
+                                                 const int32_t *__restrict__ cols,
+                                                 const typename Store<VT>::X *__restrict__ x,
+                                                 const typename Store<VT>::X *__restrict__ g,
+                                                 typename Store<VT>::A *__restrict__ gv, int64_t nnz,
+                                                 unsigned char *__restrict__ lds, int lane, bool skip_long) {
+    using A = typename Store<VT>::A;
+    constexpr int VA = 16 / int(sizeof(A));
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * VA);
+    constexpr int WIN = CAP - VA;
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    typedef int32_t CV __attribute__((ext_vector_type(VA)));
+    const int32_t r0 = rec.r0, cs = rec.e0, ce = rec.e1;
+    const int nrows = rec.r1 - rec.r0;
+    if (nrows > kWave || ce - cs > WIN) {
+        sr_grad_vals<VT>(rec.r0, rec.r1, row_ptr, cols, x, g, gv, nnz, lds, lane, skip_long);
+        return;
+    }
+    unsigned char *rowid = lds;
+    A *gwin = reinterpret_cast<A *>(lds + CAP);
+    const int32_t my_end = lane < nrows ? row_ptr[r0 + lane + 1] : 0;
+    const A gi = lane < nrows ? A(g[r0 + lane]) : A(0);
+    const int64_t base = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA;
+    int32_t c[U][VA];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * VA;
+        if (pos < ce && pos + VA <= nnz) {
+            const CV cv = *reinterpret_cast<const CV *>(cols + pos);
+#pragma unroll
+            for (int e = 0; e < VA; ++e) c[u][e] = cv[e];
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e) c[u][e] = (pos < ce && pos + e < nnz) ? cols[pos + e] : 0;
+        }
+    }
+    const int32_t prev_end = __shfl(my_end, lane > 0 ? lane - 1 : 0);
+    if (lane < nrows) {
+        gwin[lane] = gi;
+        for (int32_t k = (lane == 0 ? cs : prev_end); k < my_end; ++k) rowid[k - cs] = uint8_t(lane);
+    }
+    A xs[U][VA];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+            const int64_t k = base + int64_t(u) * kWave * VA + e;
+            xs[u][e] = (k >= cs && k < ce) ? A(x[c[u][e]]) : A(0);
+        }
+    wave_lds_sync();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * VA;
+        A out[VA];
+#pragma unroll
+        for (int e = 0; e < VA; ++e) {
+            const int64_t k = pos + e;
+            out[e] = (k >= cs && k < ce) ? gwin[rowid[k - cs]] * xs[u][e] : A(0);
+        }
+        if (pos >= cs && pos + VA <= ce) {
+            AV ov;
+#pragma unroll
+            for (int e = 0; e < VA; ++e) ov[e] = out[e];
+            *reinterpret_cast<AV *>(gv + pos) = ov;
+        } else {
+#pragma unroll
+            for (int e = 0; e < VA; ++e) {
+                const int64_t k = pos + e;
+                if (k >= cs && k < ce) gv[k] = out[e];
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
 // grad_vals for several right-hand sides: grad_vals[k] = sum_c g[i,c] x[j,c].
 // Per window, the column indices are streamed into LDS; RL lanes per row each
 // take VX columns of g_i and of the gathered x_j rows, the partial dot
@@ -1557,16 +1639,9 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs(int32_t r0, int32_t r1, co
     using X = typename Store<VT>::X;
     static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
     constexpr int V = Store<VT>::V;
-    constexpr int CAP = kStageEntries;
-    constexpr int U = CAP / (kWave * V);
-    constexpr int WIN = CAP - V;
+    constexpr int WIN = kStageEntries - V;
     constexpr int RPP = kWave / RL;
     constexpr int CPP = RL * VX;
-    constexpr int VA = 16 / int(sizeof(A));
-    typedef A AV __attribute__((ext_vector_type(VA)));
-    A *sval = reinterpret_cast<A *>(lds);
-    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
-    A *sgv = reinterpret_cast<A *>(lds + CAP * (sizeof(A) + sizeof(int32_t)));
     const int q = lane % RL;
     const int rsub = lane / RL;
     int32_t ra = r0;

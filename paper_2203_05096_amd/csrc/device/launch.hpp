@@ -64,8 +64,9 @@ struct Arrays {
     XcdSplit split_fwd;  // by the forward's work (rows of A')
     XcdSplit split_adj;  // by the adjoint's work (rows of A' and of A'^T)
     int32_t max_row = 0;  // longest row of A' or of A'^T (nonzeros)
-    const SrRec *srec = nullptr;  // nssr * srec_stride super-row records
-    int32_t srec_stride = 0;      // most super-rows in one super-super-row
+    const SrRec *srec = nullptr;    // nssr * srec_stride super-row records
+    const SrRec *srec_t = nullptr;  // the same rows of A'^T (entries of t_row_ptr); == srec if symmetric
+    int32_t srec_stride = 0;        // most super-rows in one super-super-row
 };
 
 // Per-matrix record of a batched launch (device-resident table).
