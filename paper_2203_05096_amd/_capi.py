@@ -39,7 +39,7 @@ class csrk_info(ctypes.Structure):
                 ("bandwidth_input", ctypes.c_int32), ("bandwidth", ctypes.c_int32), ("symmetry", ctypes.c_double),
                 ("max_sr_nnz", ctypes.c_int32), ("max_ssr_rows", ctypes.c_int32), ("on_device", ctypes.c_int32),
                 ("store", ctypes.c_int32), ("long_rows", ctypes.c_int32), ("values_symmetric", ctypes.c_int32),
-                ("params", csrk_params)]
+                ("params", csrk_params), ("adjoint_union", ctypes.c_int32)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "params"}

@@ -46,6 +46,11 @@ struct csrk_matrix {
     csrk::dev::XcdSplit split_fwd, split_adj;  // SSR ranges per XCD (set at upload)
     bool values_symmetric = false;  // A' == A'^T exactly: d_vals_t aliases d_vals
     int32_t max_row_any = 0;        // longest row of A' or of A'^T
+    // union pattern of a nonsymmetric A' (csrk::union_index), for the one-pass adjoint
+    int32_t *d_u_col = nullptr, *d_u_src = nullptr, *d_erow_ptr = nullptr;
+    void *d_u_vals = nullptr;
+    csrk::dev::SrRec *d_srec_u = nullptr;
+    int64_t nu = 0;
 };
 
 struct csrk_batch_s {
@@ -117,8 +122,13 @@ void free_device(csrk_matrix *h) {
     for (void *p : {(void *)h->d_row_ptr, (void *)h->d_col_idx, (void *)h->d_sr_ptr, (void *)h->d_ssr_ptr,
                     (void *)h->d_perm, (void *)h->d_t_row_ptr, (void *)h->d_t_col, (void *)h->d_t_src, h->d_vals,
                     h->d_vals_t == h->d_vals ? nullptr : h->d_vals_t, (void *)h->d_long, (void *)h->d_t_long,
-                    (void *)h->d_srec, (void *)h->d_srec_t})
+                    (void *)h->d_srec, (void *)h->d_srec_t, (void *)h->d_u_col, (void *)h->d_u_src,
+                    (void *)h->d_erow_ptr, h->d_u_vals, (void *)h->d_srec_u})
         if (p) (void)hipFree(p);
+    h->d_u_col = h->d_u_src = h->d_erow_ptr = nullptr;
+    h->d_u_vals = nullptr;
+    h->d_srec_u = nullptr;
+    h->nu = 0;
     h->d_row_ptr = h->d_col_idx = h->d_sr_ptr = h->d_ssr_ptr = h->d_perm = nullptr;
     h->d_t_row_ptr = h->d_t_col = h->d_t_src = nullptr;
     h->d_long = h->d_t_long = nullptr;
@@ -235,6 +245,12 @@ csrk::dev::Arrays arrays_of(const csrk_matrix *h) {
     a.srec = h->d_srec;
     a.srec_t = sym ? h->d_srec : h->d_srec_t;
     a.srec_stride = h->srec_stride;
+    a.u_col = h->d_u_col;
+    a.u_src = h->d_u_src;
+    a.u_vals = h->d_u_vals;
+    a.erow_ptr = h->d_erow_ptr;
+    a.srec_u = h->d_srec_u;
+    a.nu = h->nu;
     return a;
 }
 
@@ -472,6 +488,23 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
                             r.e1 = h->trans.t_row_ptr[size_t(r.r1)];
                         }
                     h->d_srec_t = upload_array(rec, "transposed super-row records");
+                    // the union pattern, when every super-row fits one staging window
+                    const csrk::UnionIndex un =
+                        csrk::union_index(h->n, h->row_ptr, h->col_idx, h->sr_ptr, h->trans, csrk::dev::kUnionRows,
+                                          csrk::dev::kUnionWindow);
+                    if (un.ok) {
+                        for (size_t t = 0; t < nssr; ++t)
+                            for (int32_t s = h->ssr_ptr[t]; s < h->ssr_ptr[t + 1]; ++s) {
+                                auto &r = rec[t * size_t(stride) + size_t(s - h->ssr_ptr[t])];
+                                r.e0 = un.sr_begin[size_t(s)];
+                                r.e1 = un.sr_end[size_t(s)];
+                            }
+                        h->nu = static_cast<int64_t>(un.u_col.size());
+                        h->d_srec_u = upload_array(rec, "union super-row records");
+                        h->d_u_col = upload_array(un.u_col, "union columns");
+                        h->d_u_src = upload_array(un.u_src, "union sources");
+                        h->d_erow_ptr = upload_array(un.erow_ptr, "union extras per row");
+                    }
                 }
             }
             if (!h->long_rows.empty()) h->d_long = upload_array(h->long_rows, "long rows");
@@ -490,12 +523,16 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
                 h->d_vals_t = h->d_vals;
             else
                 hip_check(hipMalloc(&h->d_vals_t, std::max<size_t>(1, size_t(h->nnz)) * dtype_bytes(store)), "vals_t");
+            if (h->d_u_col)
+                hip_check(hipMalloc(&h->d_u_vals, std::max<size_t>(1, size_t(h->nu)) * dtype_bytes(store)), "u_vals");
             h->on_device = true;
             if (h->nnz > 0) {
                 double *tmp = upload_array(h->vals, "vals (staging)");
                 hipError_t e = csrk::dev::convert_values(tmp, h->d_vals, h->nnz, store, nullptr);
                 if (e == hipSuccess && !h->values_symmetric)
                     e = csrk::dev::transpose_values(arrays_of(h), store, h->d_vals, h->d_vals_t, nullptr);
+                if (e == hipSuccess && h->d_u_vals)
+                    e = csrk::dev::gather_values(h->d_u_src, h->nu, store, h->d_vals, h->d_u_vals, nullptr);
                 hipError_t e2 = hipDeviceSynchronize();
                 (void)hipFree(tmp);
                 hip_check(e, "value conversion");
@@ -556,6 +593,7 @@ csrk_status csrk_get_info(csrk_handle h, csrk_info *out) {
         i.store = h->store;
         i.long_rows = static_cast<int32_t>(long_rows_of(h->row_ptr).size());
         i.values_symmetric = h->on_device && h->values_symmetric ? 1 : 0;
+        i.adjoint_union = h->on_device && h->d_srec_u ? 1 : 0;
         i.params = h->params;
         *out = i;
         return CSRK_OK;

@@ -7,7 +7,13 @@ namespace dev {
 
 namespace {
 
-template <typename VT, int L, bool IND, bool FUSED, bool ADAPT>
+// How the single-right-hand-side adjoint walks a matrix: grad_vals over A'
+// and then grad_x over the same rows of A'^T (two-phase), one pass over A'
+// for a symmetric pattern (fused), or one pass over the union pattern of a
+// nonsymmetric A' (union; srec_t then holds the union records).
+enum AdjMode { kTwoPhase = 0, kFused = 1, kUnion = 2 };
+
+template <typename VT, int L, bool IND, int MODE, bool ADAPT>
 __global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__ srec, const SrRec *__restrict__ srec_t,
                                                        int32_t stride,
                                                        const int32_t *__restrict__ row_ptr,
@@ -21,16 +27,20 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__
                                                        typename Store<VT>::A *__restrict__ gv, int64_t nnz, int sym,
                                                        const int32_t *__restrict__ long_rows, int32_t na,
                                                        const int32_t *__restrict__ t_long_rows, int32_t nt,
-                                                       int32_t long_blocks, XcdSplit split) {
+                                                       int32_t long_blocks, XcdSplit split,
+                                                       const int32_t *__restrict__ erow_ptr, int64_t nu) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
     const int32_t bid = int32_t(blockIdx.x);
     if (bid < long_blocks) {
-        if (bid < na + nt)
-            long_row_adjoint<VT, IND, FUSED>(bid, long_rows, na, t_long_rows, row_ptr, cols, t_row_ptr, t_col,
-                                             t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw, lane);
+        if constexpr (MODE != kUnion) {
+            if (bid < na + nt)
+                long_row_adjoint<VT, IND, MODE == kFused>(bid, long_rows, na, t_long_rows, row_ptr, cols, t_row_ptr,
+                                                          t_col, t_src, valsT, x, g, gx, gv, nnz, smem, wave, nw,
+                                                          lane);
+        }
         return;
     }
     unsigned char *lds = smem + size_t(wave) * kAdjointLds;
@@ -42,9 +52,13 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk(const SrRec *__restrict__
     for (int32_t w = wave; w < stride; w += nw) {
         const SrRec rec = srec[int64_t(t) * stride + w];
         if (rec.r0 >= rec.r1) break;
-        if constexpr (FUSED) {
+        if constexpr (MODE == kFused) {
             sr_adjoint_fused_rec<VT, L, IND, ADAPT>(rec, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, lds, lane,
                                                     true);
+        } else if constexpr (MODE == kUnion) {
+            // t_col / t_src / valsT are the union pattern's columns, sources and values here
+            sr_adjoint_union_rec<VT, L, IND>(rec, srec_t[int64_t(t) * stride + w], row_ptr, erow_ptr, t_col, t_src,
+                                             valsT, x, g, gx, gv, nu, lds, lane);
         } else {
             // the same rows of A'^T (grad_x = their product with g)
             const SrRec rect = srec_t[int64_t(t) * stride + w];
@@ -91,14 +105,14 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                    void *gv, int nrhs, Shape s, hipStream_t st) {
     if (a.nssr == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    // Values passed by the caller are reached through the transposed map; the
-    // handle's own values use its stored transposed copy.
+    // Values passed by the caller are reached through the transposed map (the
+    // union's source map on the union path); the handle's own values use its
+    // stored transposed (union) copy.
     const bool ind = vals != nullptr;
     return by_dtype(store, [&](auto vt) -> hipError_t {
         using VT = decltype(vt);
         using X = typename Store<VT>::X;
         using A = typename Store<VT>::A;
-        const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
         auto launch = [&](auto indc) -> hipError_t {
             constexpr bool IND = decltype(indc)::value;
             if (nrhs == 1) {
@@ -108,29 +122,39 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                     // grad_vals (and grad_x when fused), long rows of A'^T for grad_x
                     // otherwise.
                     const bool fused = a.sym && gx && gv;
-                    const int32_t na = (fused || gv) ? a.nlong : 0;
-                    const int32_t nt = (!fused && gx) ? a.t_nlong : 0;
+                    const bool adapt = adapt_windows(a, LL);
+                    // a nonsymmetric pattern whose union fits the windows takes one pass (no long rows there)
+                    const bool uni = !a.sym && gx && gv && a.srec_u && !adapt;
+                    const int32_t na = uni ? 0 : (fused || gv) ? a.nlong : 0;
+                    const int32_t nt = uni ? 0 : (!fused && gx) ? a.t_nlong : 0;
                     const int32_t long_blocks = (na + nt + kXcds - 1) / kXcds * kXcds;
-                    auto go = [&](auto fc) {
-                        constexpr bool F = decltype(fc)::value;
-                        by_adapt<LL>(adapt_windows(a, LL), [&](auto ac) {
-                            hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, F, decltype(ac)::value>),
+                    auto go = [&](auto mc) {
+                        constexpr int M = decltype(mc)::value;
+                        const VT *vsrc = static_cast<const VT *>(ind ? vals : M == kUnion ? a.u_vals : a.vals_t);
+                        const int32_t *tcol = M == kUnion ? a.u_col : a.t_col;
+                        const int32_t *tsrc = M == kUnion ? a.u_src : a.t_src;
+                        const SrRec *rec_t = M == kUnion ? a.srec_u : a.srec_t;
+                        by_adapt<LL>(M != kUnion && adapt, [&](auto ac) {
+                            hipLaunchKernelGGL((k_adjoint_csrk<VT, LL, IND, M, decltype(ac)::value>),
                                                dim3(long_blocks + a.split_adj.width * kXcds), dim3(block),
-                                               size_t(s.waves) * kAdjointLds, st, a.srec, a.srec_t, a.srec_stride,
-                                               a.row_ptr,
-                                               a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
+                                               size_t(s.waves) * kAdjointLds, st, a.srec, rec_t, a.srec_stride,
+                                               a.row_ptr, a.col_idx, a.t_row_ptr, tcol, tsrc, vsrc,
                                                static_cast<const X *>(x), static_cast<const X *>(g),
                                                static_cast<X *>(gx), static_cast<A *>(gv), a.nnz, int(a.sym),
-                                               a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj);
+                                               a.long_rows, na, a.t_long_rows, nt, long_blocks, a.split_adj,
+                                               a.erow_ptr, a.nu);
                         });
                     };
                     if (fused)
-                        go(std::true_type{});
+                        go(std::integral_constant<int, kFused>{});
+                    else if (uni)
+                        go(std::integral_constant<int, kUnion>{});
                     else
-                        go(std::false_type{});
+                        go(std::integral_constant<int, kTwoPhase>{});
                     return hipGetLastError();
                 });
             }
+            const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
             const int vx = vec_cols<X>(nrhs, {x, g, gx});
             return by_vx<X>(vx, [&](auto vc) -> hipError_t {
                 constexpr int VX = decltype(vc)::value;

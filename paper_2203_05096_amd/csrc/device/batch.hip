@@ -30,18 +30,19 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
     for (int32_t it = i0; it < i1; ++it) {
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
-        const VT *vals = static_cast<const VT *>(d.vals);
-        const X *x = static_cast<const X *>(d.x);
-        X *y = static_cast<X *>(d.y);
+        const VT *vals = global_ptr(static_cast<const VT *>(d.vals));
+        const X *x = global_ptr(static_cast<const X *>(d.x));
+        X *y = global_ptr(static_cast<X *>(d.y));
+        const int32_t *row_ptr = global_ptr(d.row_ptr), *col_idx = global_ptr(d.col_idx);
         // the item's super-rows from its records (slots past its last SR are empty)
         for (int32_t w = wave; w < stride; w += nw) {
             const SrRec rec = brec[int64_t(it) * stride + w];
             if (rec.r0 >= rec.r1) break;
             if (nrhs == 1)
-                sr_forward_rec<VT, L, false>(rec, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz,
+                sr_forward_rec<VT, L, false>(rec, row_ptr, col_idx, nullptr, vals, x, y, d.nnz,
                                              reinterpret_cast<A *>(lds) + kStagePad, lane, false);
             else
-                sr_forward_mrhs_rec<VT, L, VX, false>(rec, d.row_ptr, d.col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
+                sr_forward_mrhs_rec<VT, L, VX, false>(rec, row_ptr, col_idx, nullptr, vals, x, y, d.nnz, nrhs, lds,
                                                       lane);
         }
     }
@@ -71,25 +72,28 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
     for (int32_t it = i0; it < i1; ++it) {
         const int2 item = items[it];
         const MatDesc d = descs[item.x];
-        const VT *vals = static_cast<const VT *>(d.vals);
-        const X *x = static_cast<const X *>(d.x);
-        const X *g = static_cast<const X *>(d.g);
-        X *gx = static_cast<X *>(d.gx);
-        A *gv = static_cast<A *>(d.gv);
+        const VT *vals = global_ptr(static_cast<const VT *>(d.vals));
+        const X *x = global_ptr(static_cast<const X *>(d.x));
+        const X *g = global_ptr(static_cast<const X *>(d.g));
+        X *gx = global_ptr(static_cast<X *>(d.gx));
+        A *gv = global_ptr(static_cast<A *>(d.gv));
+        const int32_t *row_ptr = global_ptr(d.row_ptr), *col_idx = global_ptr(d.col_idx);
+        const int32_t *t_row_ptr = global_ptr(d.t_row_ptr), *t_col = global_ptr(d.t_col);
+        const int32_t *t_src = global_ptr(d.t_src);
         // the item's super-rows from its records (slots past its last SR are empty)
         for (int32_t w = wave; w < stride; w += nw) {
             const SrRec rec = brec[int64_t(it) * stride + w];
             if (rec.r0 >= rec.r1) break;
             const int32_t r0 = rec.r0, r1 = rec.r1;
             if constexpr (PATH == kAdjSingle) {
-                sr_adjoint<VT, L, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x, g, gx,
-                                       gv, d.nnz, d.sym != 0, lds, lane, false);
+                sr_adjoint<VT, L, IND>(r0, r1, row_ptr, col_idx, t_row_ptr, t_col, t_src, vals, x, g, gx, gv, d.nnz,
+                                       d.sym != 0, lds, lane, false);
             } else if constexpr (PATH == kAdjMrhsFused) {
-                sr_adjoint_fused_mrhs_rec<VT, L, VX, IND>(rec, d.row_ptr, d.col_idx, d.t_src, vals, x, g, gx, gv,
-                                                          d.nnz, nrhs, lds, lane);
+                sr_adjoint_fused_mrhs_rec<VT, L, VX, IND>(rec, row_ptr, col_idx, t_src, vals, x, g, gx, gv, d.nnz,
+                                                          nrhs, lds, lane);
             } else {
-                sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, d.row_ptr, d.col_idx, d.t_row_ptr, d.t_col, d.t_src, vals, x,
-                                                g, gx, gv, d.nnz, nrhs, d.sym != 0, lds, lane);
+                sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, row_ptr, col_idx, t_row_ptr, t_col, t_src, vals, x, g, gx, gv,
+                                                d.nnz, nrhs, d.sym != 0, lds, lane);
             }
         }
     }

@@ -16,6 +16,13 @@ namespace dev {
 // handle lists them at upload.
 constexpr int32_t kLongRow = CSRK_LONG_ROW;
 
+// A nonsymmetric pattern gets a union-pattern index (one-pass adjoint) when
+// every super-row has at most kUnionRows rows and at most kUnionWindow union
+// entries: one wavefront's staging window (512 entries) less one load step of
+// the widest entry group (8), as the window walk requires.
+constexpr int32_t kUnionRows = 64;
+constexpr int32_t kUnionWindow = 512 - 8;
+
 // Workgroups are dispatched to the 8 XCDs (each with its own L2) round-robin
 // by block index.  SSR block b (counted after the long-row blocks, a multiple
 // of 8 of them) runs super-super-row b[b % 8] + b / 8 of XCD b % 8's
@@ -67,6 +74,17 @@ struct Arrays {
     const SrRec *srec = nullptr;    // nssr * srec_stride super-row records
     const SrRec *srec_t = nullptr;  // the same rows of A'^T (entries of t_row_ptr); == srec if symmetric
     int32_t srec_stride = 0;        // most super-rows in one super-super-row
+    // Union pattern of a nonsymmetric A' (host union_index): per super-row its
+    // A' entries, then its rows' extras (entries of A'^T missing from A'),
+    // each U entry (i, j) carrying a'_ji.  Present (srec_u != nullptr) only
+    // when every super-row fits one staging window; the single-right-hand-side
+    // adjoint then takes both gradients in one pass over it.
+    const int32_t *u_col = nullptr;
+    const int32_t *u_src = nullptr;  // position of a'_ji in A', -1 where A' has no (j, i) (value 0)
+    const void *u_vals = nullptr;    // the handle's values a'_ji in U order (0 where u_src is -1)
+    const int32_t *erow_ptr = nullptr;  // extras of the rows before row i
+    const SrRec *srec_u = nullptr;      // per (SSR, slot): rows [r0, r1), U entries [e0, e1)
+    int64_t nu = 0;                     // U entries (with padding)
 };
 
 // Per-matrix record of a batched launch (device-resident table).
@@ -110,6 +128,9 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                    void *gv, int nrhs, Shape s, hipStream_t st);
 // vals_t[p] = vals[t_src[p]]: the values in A'^T order.
 hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals, void *vals_t, hipStream_t st);
+// out[p] = vals[idx[p]] (0 where idx[p] < 0) for p < count, storage type `store`.
+hipError_t gather_values(const int32_t *idx, int64_t count, csrk_dtype store, const void *vals, void *out,
+                         hipStream_t st);
 hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st);
 hipError_t convert_values(const double *src, void *dst, int64_t count, csrk_dtype store, hipStream_t st);
 

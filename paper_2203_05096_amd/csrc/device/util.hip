@@ -12,11 +12,13 @@ namespace {
 
 // ------------------------------------------------------------------ utilities
 
-// out[p] = in[idx[p]] for p < count.
+// out[p] = in[idx[p]] for p < count (0 where idx[p] < 0).
 template <typename T>
 __global__ void k_gather(const int32_t *__restrict__ idx, const T *__restrict__ in, T *__restrict__ out, int64_t count) {
-    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += int64_t(gridDim.x) * blockDim.x)
-        out[p] = in[idx[p]];
+    for (int64_t p = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += int64_t(gridDim.x) * blockDim.x) {
+        const int32_t i = idx[p];
+        out[p] = i >= 0 ? in[i] : T(0);
+    }
 }
 
 template <typename T>
@@ -124,24 +126,29 @@ hipError_t probe_copy(const void *src, void *dst, int64_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals, void *vals_t, hipStream_t st) {
-    if (a.nnz == 0) return hipSuccess;
-    const int grid = grid_for(a.nnz, 256);
+hipError_t gather_values(const int32_t *idx, int64_t count, csrk_dtype store, const void *vals, void *out,
+                         hipStream_t st) {
+    if (count == 0) return hipSuccess;
+    const int grid = grid_for(count, 256);
     switch (store) {
     case CSRK_F64:
-        hipLaunchKernelGGL((k_gather<double>), dim3(grid), dim3(256), 0, st, a.t_src, static_cast<const double *>(vals),
-                           static_cast<double *>(vals_t), a.nnz);
+        hipLaunchKernelGGL((k_gather<double>), dim3(grid), dim3(256), 0, st, idx, static_cast<const double *>(vals),
+                           static_cast<double *>(out), count);
         break;
     case CSRK_F32:
-        hipLaunchKernelGGL((k_gather<float>), dim3(grid), dim3(256), 0, st, a.t_src, static_cast<const float *>(vals),
-                           static_cast<float *>(vals_t), a.nnz);
+        hipLaunchKernelGGL((k_gather<float>), dim3(grid), dim3(256), 0, st, idx, static_cast<const float *>(vals),
+                           static_cast<float *>(out), count);
         break;
     case CSRK_BF16:
-        hipLaunchKernelGGL((k_gather<uint16_t>), dim3(grid), dim3(256), 0, st, a.t_src,
-                           static_cast<const uint16_t *>(vals), static_cast<uint16_t *>(vals_t), a.nnz);
+        hipLaunchKernelGGL((k_gather<uint16_t>), dim3(grid), dim3(256), 0, st, idx,
+                           static_cast<const uint16_t *>(vals), static_cast<uint16_t *>(out), count);
         break;
     }
     return hipGetLastError();
+}
+
+hipError_t transpose_values(const Arrays &a, csrk_dtype store, const void *vals, void *vals_t, hipStream_t st) {
+    return gather_values(a.t_src, a.nnz, store, vals, vals_t, st);
 }
 
 hipError_t permute(const Arrays &a, int dir, const void *in, void *out, int nrhs, int elem_bytes, hipStream_t st) {

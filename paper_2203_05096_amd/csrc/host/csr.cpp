@@ -1,4 +1,5 @@
-// CSR validation, the symmetric permutation A' = P A P^T, and row statistics.
+// CSR validation, the symmetric permutation A' = P A P^T, row statistics, and the
+// union-pattern index of a nonsymmetric A' for the one-pass adjoint.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -115,6 +116,72 @@ Stats row_stats(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, bool 
         s.symmetry = off ? double(mirrored) / double(off) : 1.0;
     }
     return s;
+}
+
+}  // namespace csrk
+
+namespace csrk {
+
+UnionIndex union_index(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
+                       const std::vector<int32_t> &sr_ptr, const Transposed &tr, int32_t max_rows,
+                       int32_t max_entries) {
+    UnionIndex u;
+    if (tr.symmetric || n == 0) return u;
+    const size_t nsr = sr_ptr.size() - 1;
+    // per row: the mirror source of each A' entry, and the extras
+    std::vector<int32_t> mirror(col_idx.size(), -1);
+    std::vector<int32_t> xcol, xsrc;
+    u.erow_ptr.assign(size_t(n) + 1, 0);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t k = row_ptr[i], p = tr.t_row_ptr[i];
+        const int32_t ke = row_ptr[i + 1], pe = tr.t_row_ptr[i + 1];
+        while (k < ke || p < pe) {  // both rows by increasing column
+            if (p == pe || (k < ke && col_idx[k] < tr.t_col[p])) {
+                ++k;
+            } else if (k == ke || tr.t_col[p] < col_idx[k]) {
+                xcol.push_back(tr.t_col[p]);
+                xsrc.push_back(tr.t_src[p]);
+                ++p;
+            } else {
+                mirror[size_t(k)] = tr.t_src[p];
+                ++k;
+                ++p;
+            }
+        }
+        u.erow_ptr[size_t(i) + 1] = static_cast<int32_t>(xcol.size());
+    }
+    u.sr_begin.resize(nsr);
+    u.sr_end.resize(nsr);
+    int64_t e = 0;  // U entries of earlier super-rows' extras and padding
+    for (size_t s = 0; s < nsr; ++s) {
+        const int32_t r0 = sr_ptr[s], r1 = sr_ptr[s + 1];
+        const int64_t na = row_ptr[r1] - row_ptr[r0], nx = u.erow_ptr[r1] - u.erow_ptr[r0];
+        if (r1 - r0 > max_rows || na + nx > max_entries) return {};
+        if (int64_t(row_ptr[n]) + e + nx + kUnionAlign > INT32_MAX) return {};  // U positions are int32
+        u.sr_begin[s] = static_cast<int32_t>(row_ptr[r0] + e);
+        u.sr_end[s] = static_cast<int32_t>(row_ptr[r1] + e + nx);
+        e += (nx + kUnionAlign - 1) / kUnionAlign * kUnionAlign;
+    }
+    const size_t nu = size_t(row_ptr[n] + e);
+    u.u_col.assign(nu, 0);
+    u.u_src.assign(nu, -1);
+    for (size_t s = 0; s < nsr; ++s) {
+        const int32_t r0 = sr_ptr[s], r1 = sr_ptr[s + 1];
+        size_t q = size_t(u.sr_begin[s]);
+        for (int32_t k = row_ptr[r0]; k < row_ptr[r1]; ++k, ++q) {
+            u.u_col[q] = col_idx[size_t(k)];
+            u.u_src[q] = mirror[size_t(k)];
+        }
+        for (int32_t x = u.erow_ptr[r0]; x < u.erow_ptr[r1]; ++x, ++q) {
+            u.u_col[q] = xcol[size_t(x)];
+            u.u_src[q] = xsrc[size_t(x)];
+        }
+        const int32_t nx = u.erow_ptr[r1] - u.erow_ptr[r0];
+        const size_t padded_end = size_t(u.sr_end[s]) + size_t((kUnionAlign - nx % kUnionAlign) % kUnionAlign);
+        for (; q < padded_end; ++q) u.u_col[q] = r0;  // padding: a valid column, no source (value 0)
+    }
+    u.ok = true;
+    return u;
 }
 
 }  // namespace csrk

@@ -127,6 +127,31 @@ struct Transposed {
 };
 Transposed transpose_index(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx);
 
+// Index structure of the union pattern U = pattern(A' + A'^T) of a
+// nonsymmetric A', laid out so that the adjoint can take both gradients in
+// one pass over it.  Super-row s (rows [r0, r1)) owns the U range
+// [row_ptr[r0] + e[s], row_ptr[r1] + e[s] + extras(s)): first the A' entries
+// of its rows, in A' order (column col_idx[k]; source = position in A' of the
+// mirror entry (j, i), or -1 when A' has no (j, i)), then its rows' extras:
+// for row i, the columns j with (j, i) in A' but (i, j) not in A', by
+// increasing column (source = position of (j, i) in A').  A U entry (i, j)
+// carries the value a'_ji, so row i of U times g is row i of A'^T times g.
+// e[s] is the number of U entries that earlier super-rows' extras and padding
+// take; each super-row's extras are padded (column r0, source -1) to a
+// multiple of kUnionAlign, so e[s] keeps the A' part at A''s own alignment.
+// erow_ptr[i] counts the extras of rows before i (no padding).  `ok` is false (and the vectors empty) when the
+// pattern is symmetric or some super-row has more than max_rows rows or more
+// than max_entries U entries (its A' part plus its extras).
+constexpr int32_t kUnionAlign = 8;
+struct UnionIndex {
+    bool ok = false;
+    std::vector<int32_t> u_col, u_src, erow_ptr;
+    std::vector<int32_t> sr_begin, sr_end;  // per super-row: its U range
+};
+UnionIndex union_index(int32_t n, const std::vector<int32_t> &row_ptr, const std::vector<int32_t> &col_idx,
+                       const std::vector<int32_t> &sr_ptr, const Transposed &tr, int32_t max_rows,
+                       int32_t max_entries);
+
 // Row statistics (Section 5.3 / Table 1).
 struct Stats {
     double rdensity = 0, row_variance = 0, symmetry = 1;

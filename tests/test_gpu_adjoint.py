@@ -115,6 +115,7 @@ def test_c4_full_adjoint_and_finite_differences():
     p = C.csrk_tune(A.n, A.nnz, "mi355x")
     say("c4 adjoint", p)
     M = _build(A, "f32", p)
+    assert M.info["adjoint_union"] == 1  # nonsymmetric: one pass over the union pattern
     gx, gv = _adjoint(M, x, g)
     ref_gv = OA.grad_vals(A.row_ptr, A.col_idx, x, g).astype(np.float32).astype(np.float64)
     assert np.array_equal(gv, ref_gv)
@@ -198,6 +199,58 @@ def test_adjoint_symmetric_fused(store, explicit_vals):
     assert torch.equal(gv2, gv)
     _check_grad_x(np.asarray(gx2.double().cpu().numpy())[np.argsort(perm)], A, g,
                   "f32" if store != "f64" else "f64", False, "sym partial")
+
+
+def _union_fits(s):
+    """Whether every super-row of the structure s has <= 64 rows and <= 504 entries of the union pattern (its A'
+    entries plus, per row i, the columns j with (j, i) in A' and (i, j) not in A')."""
+    rp, ci, srp = s["row_ptr"].astype(np.int64), s["col_idx"].astype(np.int64), s["sr_ptr"].astype(np.int64)
+    n = len(rp) - 1
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    lone = ~np.isin(ci * n + rows, rows * n + ci)  # (i, j) whose mirror (j, i) is absent
+    extras = np.concatenate([[0], np.cumsum(np.bincount(ci[lone], minlength=n))])
+    entries = (rp[srp[1:]] - rp[srp[:-1]]) + (extras[srp[1:]] - extras[srp[:-1]])
+    return bool(np.all(np.diff(srp) <= 64) and np.all(entries <= 504))
+
+
+@pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("explicit_vals", [False, True])
+@pytest.mark.parametrize("srs", [19, 32, 200])
+def test_adjoint_nonsymmetric_union_and_two_phase(store, explicit_vals, srs):
+    """Nonsymmetric patterns: super-rows that fit a window take one pass over the union pattern (A' + A'^T);
+    super-rows of more than 64 rows (SRS 200) keep the pass over A' and then over A'^T.  Values from the
+    handle's copies or passed in (through the union's source map, -1 where A' has no mirror entry)."""
+    A = random_sparse(3000, 5.0, seed=90 + srs, empty_row_frac=0.05)
+    if store != "f64":
+        A.vals = OP.stored_values(A.vals, store)
+    rng = np.random.default_rng(91)
+    x, g = rng.uniform(-1, 1, A.n), rng.uniform(-1, 1, A.n)
+    if store != "f64":
+        x, g = x.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
+    say("adjoint nonsymmetric", store, explicit_vals, srs)
+    M = _build(A, store, params(srs, 2, lanes=2, waves=2))
+    s = M.structure()
+    fits = _union_fits(s)
+    assert fits == (srs <= 64)  # the cases meant for each path
+    assert M.info["adjoint_union"] == int(fits)
+    perm, vmap = s["perm"], s["vmap"]
+    dt = VEC[store]
+    vals = M.values() if explicit_vals else None
+    gx, gv = M.adjoint(to_dev(x[perm], dt), to_dev(g[perm], dt), vals=vals)
+    torch.cuda.synchronize()
+    gx_in = np.empty(A.n)
+    gx_in[perm] = gx.double().cpu().numpy()
+    gv_in = np.empty(A.nnz)
+    gv_in[vmap] = gv.double().cpu().numpy()
+    ref_gv = OA.grad_vals(A.row_ptr, A.col_idx, x, g)
+    if store != "f64":
+        ref_gv = ref_gv.astype(np.float32).astype(np.float64)
+    assert np.array_equal(gv_in, ref_gv)
+    _check_grad_x(gx_in, A, g, "f32" if store != "f64" else "f64", False, f"nonsym {store} {explicit_vals} {srs}")
+    # a single output runs the two-phase path; grad_vals agrees bit for bit
+    _, gv2 = M.adjoint(to_dev(x[perm], dt), to_dev(g[perm], dt), vals=vals, grad_x=False)
+    torch.cuda.synchronize()
+    assert torch.equal(gv2, gv)
 
 
 def test_adjoint_deterministic():
