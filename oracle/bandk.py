@@ -230,6 +230,33 @@ def bandk_v1(row_ptr, col_idx, srs: int, ssrs: int):
     return np.asarray(perm, dtype=np.int64), sr_ptr, ssr_ptr
 
 
+def bandk_levels(row_ptr, col_idx, sizes):
+    """Band-k for any k >= 2 (Section 2.2 defines CSR-k for every k): ``sizes`` holds the k - 1 group sizes,
+    fine to coarse (SRS, SSRS, ...).  G_l = Quotient(Aggregate(G_{l-1}, sizes[l-1])) for l = 1 .. k-1; the
+    coarsest level is ordered by RCM(G_{k-1}); then each level is expanded into the one below it,
+    order_{l-1} = Expand(G_{l-1}, order_l), down to the rows (perm = order_0).  Returns ``(perm, ptrs)``
+    where ptrs[l-1] is the pointer array of level l: running counts of level-(l-1) units per level-l unit in
+    order_l (ptrs[0] = sr_ptr counts rows per SR, ptrs[1] = ssr_ptr counts SRs per SSR, ...)."""
+    sizes = [int(t) for t in sizes]
+    if not sizes or any(t < 1 for t in sizes):
+        raise ValueError("k - 1 >= 1 group sizes, each >= 1")
+    G = [graph_from_csr(row_ptr, col_idx)]
+    if G[0].n == 0:
+        return np.zeros(0, np.int64), [np.zeros(1, np.int64) for _ in sizes]
+    children = []
+    for t in sizes:  # coarsen k - 1 times
+        agg, ch, ident = aggregate(G[-1], t)
+        children.append(ch)
+        G.append(quotient(G[-1], agg, ident))
+    order = reverse_cuthill_mckee(G[-1])
+    ptrs = []
+    for lvl in range(len(sizes), 0, -1):  # expand level lvl into level lvl - 1
+        ptrs.append(running_counts([len(children[lvl - 1][u]) for u in order]))
+        order = expand(G[lvl - 1], order, children[lvl - 1])
+    ptrs.reverse()
+    return np.asarray(order, dtype=np.int64), ptrs
+
+
 def bandk_k2(row_ptr, col_idx, srs: int, group: int):
     """Band-k with k = 2 (CSR-2): G1 = Quotient(Aggregate(G0, SRS)); the SRs are the vertices of G1 in
     RCM(G1) order; perm = Expand(G0, that order).  CSR-2 has no SSR level: for the launch the SRs are grouped
@@ -302,8 +329,13 @@ def bandwidth(row_ptr, col_idx) -> int:
 
 def build_grouping(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk", k: int = 3):
     """Ordering + grouping of steps 1-7: Band-k with k levels, RCM with fixed chunks, or the input order with
-    fixed chunks."""
-    if reorder == "bandk":
+    fixed chunks.  For k >= 4 every level above the SR groups SSRS units of the level below (the reading of
+    this project: the paper gives sizes only for k <= 3); the SR and SSR levels are returned here, the higher
+    ones by ``upper_levels``."""
+    if reorder == "bandk" and k >= 4:
+        perm, ptrs = bandk_levels(row_ptr, col_idx, [srs] + [ssrs] * (k - 2))
+        sr_ptr, ssr_ptr = ptrs[0], ptrs[1]
+    elif reorder == "bandk":
         perm, sr_ptr, ssr_ptr = (bandk_v1 if k == 3 else bandk_k2)(row_ptr, col_idx, srs, ssrs)
     elif reorder == "rcm":
         perm, sr_ptr, ssr_ptr = reorder_rcm(row_ptr, col_idx, srs, ssrs)
@@ -311,3 +343,18 @@ def build_grouping(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk"
         perm, sr_ptr, ssr_ptr = reorder_none(len(row_ptr) - 1, srs, ssrs)
     return perm, sr_ptr, ssr_ptr
 
+
+def upper_levels(row_ptr, col_idx, srs: int, ssrs: int, reorder: str = "bandk", k: int = 4):
+    """Pointer arrays of levels 3 .. k-1 (level l counts level-(l-1) units per level-l unit), k >= 4: from
+    Band-k, or for the RCM / input orders consecutive chunks of SSRS units of the level below."""
+    if k < 4:
+        return []
+    if reorder == "bandk":
+        return bandk_levels(row_ptr, col_idx, [srs] + [ssrs] * (k - 2))[1][2:]
+    _, _, ssr_ptr = build_grouping(row_ptr, col_idx, srs, ssrs, reorder, 3)
+    units, out = len(ssr_ptr) - 1, []
+    for _ in range(k - 3):
+        sizes = [min(ssrs, units - t) for t in range(0, units, ssrs)]
+        out.append(running_counts(sizes))
+        units = len(sizes)
+    return out

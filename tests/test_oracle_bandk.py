@@ -195,3 +195,61 @@ def test_csr2_srs1_is_rcm_and_invariants():
     y[perm] = y2
     assert np.allclose(y, O.spmv(A.row_ptr, A.col_idx, A.vals, x), rtol=0, atol=1e-12)
 
+
+# ------------------------------------------------------------------ CSR-k for k >= 4 (Section 2.2: any k)
+
+def test_worked_example_path16_k4(golden_dir):
+    g = _read_golden(os.path.join(golden_dir, "bandk_path16_k4.txt"))
+    rp, ci = _path(g["n"][0])
+    perm, ptrs = B.bandk_levels(rp, ci, g["sizes"])
+    assert perm.tolist() == g["perm"]
+    assert [p.tolist() for p in ptrs] == [g["level1_ptr"], g["level2_ptr"], g["level3_ptr"]]
+
+
+@pytest.mark.parametrize("srs,ssrs", [(4, 3), (1, 1), (7, 2)])
+def test_levels_reduce_to_k3_and_k2(srs, ssrs):
+    """Two and three levels of the general walk are the k = 3 and k = 2 forms (pinned separately)."""
+    for A in (workload_c1()["A"], random_sparse(400, 3.0, seed=srs, empty_row_frac=0.1)):
+        perm, ptrs = B.bandk_levels(A.row_ptr, A.col_idx, [srs, ssrs])
+        p3 = B.bandk_v1(A.row_ptr, A.col_idx, srs, ssrs)
+        assert np.array_equal(perm, p3[0]) and np.array_equal(ptrs[0], p3[1]) and np.array_equal(ptrs[1], p3[2])
+        perm2, ptrs2 = B.bandk_levels(A.row_ptr, A.col_idx, [srs])
+        p2 = B.bandk_k2(A.row_ptr, A.col_idx, srs, ssrs)
+        assert np.array_equal(perm2, p2[0]) and np.array_equal(ptrs2[0], p2[1])
+
+
+def test_levels_unit_sizes_reduce_to_rcm():
+    A = workload_c1()["A"]
+    perm, ptrs = B.bandk_levels(A.row_ptr, A.col_idx, [1, 1, 1, 1])
+    assert perm.tolist() == B.reverse_cuthill_mckee(B.graph_from_csr(A.row_ptr, A.col_idx))
+    assert all(p.tolist() == list(range(A.n + 1)) for p in ptrs)
+
+
+@pytest.mark.parametrize("seed,sym,sizes", [(0, True, [4, 3, 2]), (1, False, [8, 2, 3, 2]), (2, False, [3, 5, 5]),
+                                            (3, True, [2, 2, 2, 2, 2])])
+def test_levels_invariants_random(seed, sym, sizes):
+    A = random_sparse(300, 3.0, seed=seed, empty_row_frac=0.1, symmetric_pattern=sym)
+    perm, ptrs = B.bandk_levels(A.row_ptr, A.col_idx, sizes)
+    assert sorted(perm.tolist()) == list(range(A.n))
+    units = A.n
+    for p, t in zip(ptrs, sizes):
+        assert p[0] == 0 and p[-1] == units
+        assert np.all(np.diff(p) >= 1) and np.all(np.diff(p) <= t)
+        units = len(p) - 1
+    assert units >= 1
+    r2, c2, v2, vm = B.apply_permutation(A.row_ptr, A.col_idx, A.vals, perm)
+    x = np.random.default_rng(seed).uniform(-1, 1, A.n)
+    y = O.spmv(A.row_ptr, A.col_idx, A.vals, x)
+    scale = O.row_abs_sum(A.row_ptr, A.col_idx, A.vals, x)
+    assert np.all(np.abs(O.spmv(r2, c2, v2, x[perm]) - y[perm]) <= 1e-12 * scale[perm])
+
+
+def test_upper_levels_chunk_the_level_below():
+    A = random_sparse(500, 4.0, seed=9)
+    for reorder in ("rcm", "none"):
+        _, _, ssr_ptr = B.build_grouping(A.row_ptr, A.col_idx, 5, 3, reorder, 3)
+        up = B.upper_levels(A.row_ptr, A.col_idx, 5, 3, reorder, 5)
+        assert len(up) == 2
+        assert up[0][-1] == len(ssr_ptr) - 1 and np.all(np.diff(up[0]) == np.minimum(3, (len(ssr_ptr) - 1) - up[0][:-1]))
+        assert up[1][-1] == len(up[0]) - 1
+
