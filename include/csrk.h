@@ -76,10 +76,15 @@ typedef enum csrk_reorder { CSRK_REORDER_BANDK = 0, CSRK_REORDER_RCM = 1, CSRK_R
 /* Tuning parameters.  srs = rows per super-row (SRS), ssrs = super-rows per
  * super-super-row (SSRS) (Section 4.1).  lanes_per_row (1, 2, 4, ..., 64) is
  * the number of wavefront lanes that reduce one row; waves_per_wg (1..16) the
- * wavefronts per workgroup.  k is 3 (CSR-3) or 2 (CSR-2, Section 2.2: one
+ * wavefronts per workgroup.  k is the number of CSR-k levels, 2..8 (Section
+ * 2.2 defines CSR-k for every k >= 2): k - 1 grouping levels above the rows.
+ * k = 3 (CSR-3): super-rows and super-super-rows.  k = 2 (CSR-2): one
  * coarsening level, Band-k orders the coarse graph by reverse Cuthill-McKee;
  * the super-rows are then grouped ssrs at a time in order for the launch,
- * which is what ssr_ptr holds for k = 2). */
+ * which is what ssr_ptr holds for k = 2.  k >= 4: every level above the
+ * super-row groups ssrs units of the level below (this library's reading; the
+ * paper sizes only k <= 3), Band-k coarsens k - 1 times; the GPU kernels use
+ * the super-row and super-super-row levels, csrk_level_ptr gives the others. */
 typedef struct csrk_params {
     int32_t k;
     int32_t srs;
@@ -185,7 +190,8 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
  * ordering perm[n] (perm[new] = old) and grouping: nsr super-rows of
  * sr_sizes[s] >= 1 rows each (sum = n) and nssr super-super-rows of
  * ssr_sizes[t] >= 1 super-rows each (sum = nsr).  This is how uneven groups
- * such as those of Fig. 1 are expressed.
+ * such as those of Fig. 1 are expressed.  p->k must be 2 or 3 here (the
+ * caller gives two levels); CSRK_ERR_ARG otherwise.
  */
 csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                                    const void *vals, csrk_dtype in_dtype, const int32_t *perm, int32_t nsr,
@@ -217,6 +223,17 @@ csrk_status csrk_set_launch(csrk_handle h, int32_t lanes_per_row, int32_t waves_
 
 /* Statistics and parameters of a handle. */
 csrk_status csrk_get_info(csrk_handle h, csrk_info *out);
+
+/*
+ * csrk_level_ptr — the pointer array of grouping level `level` (Section 2.2,
+ * Fig. 1): level 1 = sr_ptr (rows per super-row), level 2 = ssr_ptr
+ * (super-rows per super-super-row), level l >= 3 (k >= 4) = running counts of
+ * level-(l-1) units per level-l unit.  Valid levels: 1 .. max(2, k - 1).
+ * *count receives the number of level-l units; out, if not NULL, must hold
+ * *count + 1 entries and receives the array.  Host only.
+ * Errors: CSRK_ERR_ARG (null handle or count, level out of range).
+ */
+csrk_status csrk_level_ptr(csrk_handle h, int32_t level, int32_t *count, int32_t *out);
 
 /*
  * csrk_copy_structure — copy the host structure into caller buffers; any

@@ -83,6 +83,7 @@ _SIGS = {
     "csrk_set_launch": ([_h, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "csrk_get_info": ([_h, ctypes.POINTER(csrk_info)], ctypes.c_int),
     "csrk_copy_structure": ([_h, _i32p, _i32p, _i32p, _f64p, _i64p, _i32p, _i32p], ctypes.c_int),
+    "csrk_level_ptr": ([_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp], ctypes.c_int),
     "csrk_device_vals": ([_h, ctypes.POINTER(_vp)], ctypes.c_int),
     "csrk_copy_device_vals": ([_h, _vp, _vp], ctypes.c_int),
     "csrk_spmv": ([_h, _vp, _vp, _vp, ctypes.c_int32, _vp], ctypes.c_int),
@@ -262,6 +263,15 @@ def csrk_copy_structure(h: int) -> dict:
     _check(lib().csrk_copy_structure(h, _ptr(out["perm"], _i32p), _ptr(out["row_ptr"], _i32p),
                                      _ptr(out["col_idx"], _i32p), _ptr(out["vals"], _f64p), _ptr(out["vmap"], _i64p),
                                      _ptr(out["sr_ptr"], _i32p), _ptr(out["ssr_ptr"], _i32p)), "csrk_copy_structure")
+    return out
+
+
+def csrk_level_ptr(h: int, level: int) -> np.ndarray:
+    """Pointer array of grouping level `level` (1 = sr_ptr, 2 = ssr_ptr, 3 .. k-1 higher levels)."""
+    count = ctypes.c_int32(0)
+    _check(lib().csrk_level_ptr(h, level, ctypes.byref(count), None), "csrk_level_ptr")
+    out = np.empty(count.value + 1, dtype=np.int32)
+    _check(lib().csrk_level_ptr(h, level, ctypes.byref(count), out.ctypes.data_as(_vp)), "csrk_level_ptr")
     return out
 
 

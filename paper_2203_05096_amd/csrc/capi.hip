@@ -24,6 +24,7 @@ struct csrk_matrix {
     int64_t nnz = 0;
     csrk_params params{};
     std::vector<int32_t> perm, row_ptr, col_idx, sr_ptr, ssr_ptr;
+    std::vector<std::vector<int32_t>> upper_ptr;  // grouping levels 3 .. k-1 (k >= 4)
     std::vector<int64_t> vmap;
     std::vector<double> vals;
     csrk::Stats in_stats, out_stats;
@@ -157,6 +158,7 @@ void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx,
     h->perm = std::move(gr.perm);
     h->sr_ptr = std::move(gr.sr_ptr);
     h->ssr_ptr = std::move(gr.ssr_ptr);
+    h->upper_ptr = std::move(gr.upper);
     h->row_ptr = std::move(pm.row_ptr);
     h->col_idx = std::move(pm.col_idx);
     h->vals = std::move(pm.vals);
@@ -388,15 +390,21 @@ csrk_status csrk_build_host(int32_t n, int64_t nnz, const int32_t *row_ptr, cons
         const double *vals = values_as_f64(vals_in, in_dtype, nnz, widened);
         csrk_params q = resolve_params(n, nnz, p);
         csrk::Grouping gr;
-        if (q.reorder == CSRK_REORDER_BANDK) {
+        if (q.reorder == CSRK_REORDER_BANDK && q.k >= 4) {
+            std::vector<int32_t> sizes(size_t(q.k) - 1, q.ssrs);
+            sizes[0] = q.srs;
+            gr = csrk::bandk_levels(n, row_ptr, col_idx, sizes);
+        } else if (q.reorder == CSRK_REORDER_BANDK) {
             gr = q.k == 2 ? csrk::bandk2(n, row_ptr, col_idx, q.srs, q.ssrs)
                           : csrk::bandk(n, row_ptr, col_idx, q.srs, q.ssrs);
         } else if (q.reorder == CSRK_REORDER_RCM) {
             gr = csrk::rcm_chunked(n, row_ptr, col_idx, q.srs, q.ssrs);
+            csrk::chunk_upper(gr, q.k, q.ssrs);
         } else {
             std::vector<int32_t> id(n);
             std::iota(id.begin(), id.end(), 0);
             gr = csrk::chunked(std::move(id), q.srs, q.ssrs);
+            csrk::chunk_upper(gr, q.k, q.ssrs);
         }
         csrk::balance(gr, row_ptr, csrk::sr_budget(n, nnz, q.srs), q.ssrs);
         auto h = new csrk_matrix();
@@ -426,6 +434,7 @@ csrk_status csrk_build_from_groups(int32_t n, int64_t nnz, const int32_t *row_pt
         const double *vals = values_as_f64(vals_in, in_dtype, nnz, widened);
         if (n > 0 && !perm) throw Error{CSRK_ERR_ARG, "perm is NULL"};
         csrk_params q = resolve_params(n, nnz, p);
+        if (q.k > 3) throw Error{CSRK_ERR_ARG, "csrk_build_from_groups takes two grouping levels: k must be 2 or 3"};
         csrk::Grouping gr = csrk::from_sizes(std::vector<int32_t>(perm, perm + n), sr_sizes, nsr, ssr_sizes, nssr);
         auto h = new csrk_matrix();
         try {
@@ -614,6 +623,19 @@ csrk_status csrk_copy_structure(csrk_handle h, int32_t *perm, int32_t *row_ptr, 
         cp(vmap, h->vmap);
         cp(sr_ptr, h->sr_ptr);
         cp(ssr_ptr, h->ssr_ptr);
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_level_ptr(csrk_handle h, int32_t level, int32_t *count, int32_t *out) {
+    return guard([&] {
+        if (!h || !count) throw Error{CSRK_ERR_ARG, "null handle or count"};
+        const int32_t top = std::max(2, h->params.k - 1);
+        if (level < 1 || level > top) throw Error{CSRK_ERR_ARG, "level out of range (1 .. max(2, k - 1))"};
+        const std::vector<int32_t> &v =
+            level == 1 ? h->sr_ptr : level == 2 ? h->ssr_ptr : h->upper_ptr[size_t(level) - 3];
+        *count = static_cast<int32_t>(v.size()) - 1;
+        if (out) std::memcpy(out, v.data(), v.size() * sizeof(int32_t));
         return CSRK_OK;
     });
 }

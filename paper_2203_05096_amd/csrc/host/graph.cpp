@@ -248,6 +248,51 @@ Grouping bandk(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_
     return r;
 }
 
+Grouping bandk_levels(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const std::vector<int32_t> &sizes) {
+    if (sizes.empty()) throw Error{CSRK_ERR_ARG, "at least one group size"};
+    for (int32_t t : sizes)
+        if (t < 1) throw Error{CSRK_ERR_ARG, "group sizes must be >= 1"};
+    const size_t levels = sizes.size();
+    std::vector<std::vector<int32_t>> ptr(levels, std::vector<int32_t>{0});
+    Grouping r;
+    if (n > 0) {
+        std::vector<Graph> g;
+        std::vector<Aggregation> agg;
+        g.push_back(graph_from_csr(n, row_ptr, col_idx));
+        for (size_t l = 0; l < levels; ++l) {  // coarsen k - 1 times
+            agg.push_back(aggregate(g.back(), sizes[l]));
+            g.push_back(quotient(g.back(), agg.back()));
+        }
+        std::vector<int32_t> order = cuthill_mckee(g.back());
+        std::reverse(order.begin(), order.end());
+        for (size_t l = levels; l >= 1; --l) {  // expand level l into level l - 1
+            const Aggregation &a = agg[l - 1];
+            std::vector<int64_t> sz;
+            sz.reserve(order.size());
+            for (int32_t u : order) sz.push_back(a.child_ptr[u + 1] - a.child_ptr[u]);
+            ptr[l - 1] = running(sz);
+            order = expand(g[l - 1], order, a);
+        }
+        r.perm = std::move(order);
+    }
+    r.sr_ptr = std::move(ptr[0]);
+    if (levels >= 2) r.ssr_ptr = std::move(ptr[1]);
+    for (size_t l = 2; l < levels; ++l) r.upper.push_back(std::move(ptr[l]));
+    return r;
+}
+
+void chunk_upper(Grouping &g, int32_t k, int32_t t) {
+    if (t < 1) throw Error{CSRK_ERR_ARG, "group size must be >= 1"};
+    g.upper.clear();
+    int64_t units = int64_t(g.ssr_ptr.size()) - 1;
+    for (int32_t l = 3; l < k; ++l) {
+        std::vector<int64_t> sz;
+        for (int64_t u = 0; u < units; u += t) sz.push_back(std::min<int64_t>(t, units - u));
+        g.upper.push_back(running(sz));
+        units = int64_t(sz.size());
+    }
+}
+
 Grouping bandk2(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t group) {
     if (srs < 1 || group < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
     Grouping r;
@@ -368,8 +413,17 @@ void balance(Grouping &g, const int32_t *row_ptr, int64_t budget, int32_t ssrs) 
         for (int32_t q = 0; q < pieces; q += ssrs) ssr_sizes.push_back(std::min<int64_t>(ssrs, pieces - q));
     }
     if (!split_any) return;
+    // rows where each level-3 unit starts, to recount it over the new SSRs
+    std::vector<int32_t> start_rows;
+    if (!g.upper.empty())
+        for (int32_t u : g.upper[0]) start_rows.push_back(g.sr_ptr[g.ssr_ptr[u]]);
     g.sr_ptr = running(sr_sizes);
     g.ssr_ptr = running(ssr_sizes);
+    size_t t = 0;
+    for (size_t q = 0; q < start_rows.size(); ++q) {
+        while (g.sr_ptr[g.ssr_ptr[t]] < start_rows[q]) ++t;  // the new SSR that starts at this row
+        g.upper[0][q] = static_cast<int32_t>(t);
+    }
 }
 
 }  // namespace csrk

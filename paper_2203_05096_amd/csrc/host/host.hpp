@@ -68,15 +68,32 @@ Graph quotient(const Graph &g, const Aggregation &a);
 std::vector<int32_t> expand(const Graph &g, const std::vector<int32_t> &order_up, const Aggregation &a);
 
 // Ordering + grouping result: perm[new] = old; sr_ptr / ssr_ptr running counts.
+// For k >= 4, upper[l - 3] is the pointer array of grouping level l = 3 .. k-1
+// (running counts of level-(l-1) units per level-l unit; level 2 is the SSR).
 struct Grouping {
     std::vector<int32_t> perm;
     std::vector<int32_t> sr_ptr;
     std::vector<int32_t> ssr_ptr;
+    std::vector<std::vector<int32_t>> upper;
 };
+
+// Largest k accepted (CSR-k is defined for every k >= 2, Section 2.2).
+constexpr int32_t kMaxK = 8;
 
 // Band-k with k = 3 (Section 2.2): coarsen by SRS, coarsen again by SSRS,
 // reverse Cuthill-McKee of the coarsest graph, expand twice.
 Grouping bandk(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, int32_t srs, int32_t ssrs);
+
+// Band-k with any k >= 2 levels of pointers: coarsen k - 1 times by the group
+// sizes sizes[0..k-2] (fine to coarse), reverse Cuthill-McKee of the coarsest
+// graph, expand level by level.  Fills sr_ptr (level 1), ssr_ptr (level 2;
+// for k = 2 the super-rows grouped sizes[0]... see bandk2) and upper.  For
+// k = 3 the result is bandk's.
+Grouping bandk_levels(int32_t n, const int32_t *row_ptr, const int32_t *col_idx, const std::vector<int32_t> &sizes);
+
+// Levels 3 .. k-1 over a grouping whose SR and SSR levels exist: consecutive
+// chunks of `t` units of the level below (orders other than Band-k).
+void chunk_upper(Grouping &g, int32_t k, int32_t t);
 
 // Band-k with k = 2 (CSR-2): coarsen once by SRS, reverse Cuthill-McKee of the
 // coarse graph, expand.  The format has no super-super-row level; for the GPU
@@ -98,6 +115,8 @@ int64_t sr_budget(int32_t n, int64_t nnz, int32_t srs);
 // CSRK_LONG_ROW counted as 0) exceeds `budget` greedily into consecutive
 // pieces of cost <= budget, and regroups the pieces of each super-super-row
 // `ssrs` at a time.  row_ptr is the input matrix's (rows in input order).
+// Levels above the SSR keep their row ranges: upper[0] is recounted over the
+// new SSRs (every old SSR start is still an SSR start).
 void balance(Grouping &g, const int32_t *row_ptr, int64_t budget, int32_t ssrs);
 
 // ---------------------------------------------------------------- CSR

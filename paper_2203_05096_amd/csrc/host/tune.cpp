@@ -149,7 +149,7 @@ csrk_status tune_rhs(int64_t n, int64_t nnz, int32_t nrhs, csrk_model model, csr
 }
 
 void check_params(const csrk_params &p) {
-    if (p.k != 2 && p.k != 3) throw Error{CSRK_ERR_ARG, "k must be 2 or 3"};
+    if (p.k < 2 || p.k > kMaxK) throw Error{CSRK_ERR_ARG, "k must be in 2..8"};
     if (p.srs < 1 || p.ssrs < 1) throw Error{CSRK_ERR_ARG, "srs and ssrs must be >= 1"};
     const int L = p.lanes_per_row;
     if (L < 1 || L > 64 || (L & (L - 1))) throw Error{CSRK_ERR_ARG, "lanes_per_row must be a power of two in 1..64"};

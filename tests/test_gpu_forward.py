@@ -77,7 +77,8 @@ def test_random_ragged_all_precisions(store, reorder):
 
 @pytest.mark.parametrize("store", ["f64", "f32"])
 def test_csr2_forward_and_adjoint(store):
-    """k = 2 (one grouping level): same kernels over the CSR-2 structure."""
+    """k = 2 (one grouping level) and k = 4, 5 (levels above the super-super-row shape the ordering only):
+    the same kernels over each structure."""
     from oracle import adjoint as OA
     A = random_sparse(4001, 7.0, seed=19, empty_row_frac=0.05, symmetric_pattern=False)
     rng = np.random.default_rng(20)
@@ -85,10 +86,11 @@ def test_csr2_forward_and_adjoint(store):
     if store != "f64":
         A.vals = OP.stored_values(A.vals, store)
         x, g = x.astype(np.float32).astype(np.float64), g.astype(np.float32).astype(np.float64)
-    for p in (params(24, 2, lanes=2, waves=2, k=2), params(64, 4, lanes=1, waves=4, k=2)):
-        say("csr2", store, p)
+    for p in (params(24, 2, lanes=2, waves=2, k=2), params(64, 4, lanes=1, waves=4, k=2),
+              params(16, 2, lanes=2, waves=2, k=4), params(8, 3, lanes=1, waves=3, k=5)):
+        say("csr-k", store, p)
         M = _build(A, store, p)
-        assert M.info["params"]["k"] == 2
+        assert M.info["params"]["k"] == p["k"]
         y, perm = _run(M, x)
         check_forward(y, A, x, perm, store, False, label=f"csr2 {store}")
         s = M.structure()

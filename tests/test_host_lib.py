@@ -128,6 +128,77 @@ def test_bitexact_random(seed, sym, srs, ssrs, empty):
     _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, srs, ssrs)
 
 
+@pytest.mark.parametrize("k,seed,sym,srs,ssrs", [(4, 0, True, 4, 3), (4, 1, False, 8, 2), (5, 2, False, 3, 3),
+                                                 (6, 3, True, 2, 2), (8, 4, False, 2, 2), (4, 5, True, 1, 1)])
+def test_bitexact_general_k(k, seed, sym, srs, ssrs):
+    """CSR-k for k >= 4 (Section 2.2): Band-k with k - 1 coarsening levels, every level bit for bit with the
+    oracle, including the levels above the super-super-row (csrk_level_ptr)."""
+    A = random_sparse(500, 4.0, seed=seed, empty_row_frac=0.1, symmetric_pattern=sym)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, srs, ssrs, "bandk", k)
+    up = OB.upper_levels(A.row_ptr, A.col_idx, srs, ssrs, "bandk", k)
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, _params(srs, ssrs, "bandk", k))
+    try:
+        assert np.array_equal(C.csrk_level_ptr(h, 1), C.csrk_copy_structure(h)["sr_ptr"])
+        for lvl, ref in enumerate(up, start=3):
+            assert np.array_equal(C.csrk_level_ptr(h, lvl), ref)
+        with pytest.raises(C.CsrkError):
+            C.csrk_level_ptr(h, k)
+        with pytest.raises(C.CsrkError):
+            C.csrk_level_ptr(h, 0)
+    finally:
+        C.csrk_destroy(h)
+
+
+def test_general_k_path16_golden(golden_dir):
+    """The hand-derived k = 4 example (tests/golden/bandk_path16_k4.txt) through the library."""
+    rp, ci = _path(16)
+    s, _ = _assert_same_as_oracle(rp, ci, np.arange(len(ci), dtype=np.float64), 2, 2, "bandk", 4)
+    assert s["perm"].tolist() == list(range(15, -1, -1))
+    h = C.csrk_build_host(rp, ci, None, _params(2, 2, "bandk", 4))
+    try:
+        assert C.csrk_level_ptr(h, 3).tolist() == [0, 2, 4]
+    finally:
+        C.csrk_destroy(h)
+
+
+@pytest.mark.parametrize("reorder", ["rcm", "none"])
+def test_general_k_other_orders(reorder):
+    A = random_sparse(300, 5.0, seed=19, empty_row_frac=0.1)
+    _assert_same_as_oracle(A.row_ptr, A.col_idx, A.vals, 6, 3, reorder, 5)
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, _params(6, 3, reorder, 5))
+    try:
+        for lvl, ref in enumerate(OB.upper_levels(A.row_ptr, A.col_idx, 6, 3, reorder, 5), start=3):
+            assert np.array_equal(C.csrk_level_ptr(h, lvl), ref)
+    finally:
+        C.csrk_destroy(h)
+
+
+def test_general_k_irregular_split_keeps_upper_levels():
+    """On an irregular matrix the super-row split refines the SR and SSR levels; the level above the SSR keeps
+    its row ranges (each of its units starts where it started, now counted in the new SSRs)."""
+    from gen.irregular import rmat_matrix
+    A = rmat_matrix(scale=12, edge_factor=8, seed=3)
+    k, srs, ssrs = 4, 64, 2
+    up = OB.upper_levels(A.row_ptr, A.col_idx, srs, ssrs, "bandk", k)[0]
+    _, sr0, ssr0 = OB.build_grouping(A.row_ptr, A.col_idx, srs, ssrs, "bandk", k)
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, _params(srs, ssrs, "bandk", k))
+    try:
+        s = C.csrk_copy_structure(h)
+        lib_up = C.csrk_level_ptr(h, 3)
+        assert len(s["sr_ptr"]) > len(sr0)  # the split happened
+        rows_ref = sr0[ssr0[up]]
+        rows_lib = s["sr_ptr"][s["ssr_ptr"][lib_up]]
+        assert np.array_equal(rows_ref, rows_lib)
+    finally:
+        C.csrk_destroy(h)
+
+
+def test_from_groups_rejects_k4():
+    rp, ci = _path(8)
+    with pytest.raises(C.CsrkError):
+        C.csrk_build_from_groups(rp, ci, None, np.arange(8), [4, 4], [2], _params(4, 2, "bandk", 4))
+
+
 @pytest.mark.parametrize("reorder", ["rcm", "none"])
 def test_bitexact_other_orders(reorder):
     A = random_sparse(300, 5.0, seed=9, empty_row_frac=0.1)
