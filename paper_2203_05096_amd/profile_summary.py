@@ -160,6 +160,22 @@ def counters(args):
                       "per active LDS cycle.", "",
                   "| kernel | L2 hit | L2 misses x 128 B (MB) | wait share | LDS conflicts / LDS active |",
                   "|---|---|---|---|---|", *rows]
+    # per-CU busy shares: TA / TD / TCP counters are summed over the 256 CUs, GRBM_GUI_ACTIVE over the 8 XCDs
+    rows = []
+    for k in kept:
+        act = mean(k, "GRBM_GUI_ACTIVE")
+        if not act:
+            continue
+        share = lambda c: mean(k, c) / 256 / (act / 8) if mean(k, c) is not None else None  # noqa: E731
+        vals = [share(c) for c in ("TA_TA_BUSY_sum", "TD_TD_BUSY_sum", "TCP_PENDING_STALL_CYCLES_sum")]
+        if all(v is None for v in vals):
+            continue
+        rows.append(f"| `{k}` | " + " | ".join("" if v is None else f"{v:.2f}" for v in vals) + " |")
+    if rows:
+        lines += ["", "Vector-memory pipeline, share of the active cycles per CU (counters summed over the 256 CUs, "
+                      "GRBM_GUI_ACTIVE over the 8 XCDs): texture-address unit busy, texture-data unit busy, L1 "
+                      "waiting for L2 data.", "",
+                  "| kernel | TA busy | TD busy | L1 pending on L2 |", "|---|---|---|---|", *rows]
     print("\n".join(lines))
 
 
