@@ -236,6 +236,24 @@ csrk_status csrk_get_info(csrk_handle h, csrk_info *out);
 csrk_status csrk_level_ptr(csrk_handle h, int32_t level, int32_t *count, int32_t *out);
 
 /*
+ * csrk_copy_union — the union-pattern index a nonsymmetric A' gets for its
+ * one-pass adjoint (built on the host with the structure; see adjoint_union
+ * in csrk_info).  *nu receives the number of union entries, padding included
+ * (0 when the pattern is symmetric or some super-row has more than 64 rows or
+ * more than 504 union entries: then the adjoint walks A' and A'^T).  Super-row
+ * s owns union entries [sr_begin[s], sr_end[s]): its A' entries in A' order
+ * (u_col = their columns), then its rows' extras, the columns j with (j, i) in
+ * A' but (i, j) not, row by row by increasing column; each super-row's extras
+ * are padded (column = its first row, source -1) to a multiple of 8.  u_src
+ * gives the position in A' of the mirror entry (j, i) of union entry (i, j),
+ * -1 where A' has none; erow_ptr[n+1] counts extras before each row (no
+ * padding).  Buffers: u_col[nu], u_src[nu], erow_ptr[n+1], sr_begin[nsr],
+ * sr_end[nsr]; any may be NULL.  Host only.  Errors: CSRK_ERR_ARG.
+ */
+csrk_status csrk_copy_union(csrk_handle h, int64_t *nu, int32_t *u_col, int32_t *u_src, int32_t *erow_ptr,
+                            int32_t *sr_begin, int32_t *sr_end);
+
+/*
  * csrk_copy_structure — copy the host structure into caller buffers; any
  * pointer may be NULL.  perm[n], row_ptr[n+1], col_idx[nnz] and vals[nnz]
  * (FP64 master values) describe A' as plain CSR, which is what keeps CSR-k

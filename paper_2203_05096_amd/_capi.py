@@ -83,6 +83,7 @@ _SIGS = {
     "csrk_set_launch": ([_h, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "csrk_get_info": ([_h, ctypes.POINTER(csrk_info)], ctypes.c_int),
     "csrk_copy_structure": ([_h, _i32p, _i32p, _i32p, _f64p, _i64p, _i32p, _i32p], ctypes.c_int),
+    "csrk_copy_union": ([_h, ctypes.POINTER(ctypes.c_int64), _vp, _vp, _vp, _vp, _vp], ctypes.c_int),
     "csrk_level_ptr": ([_h, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _vp], ctypes.c_int),
     "csrk_device_vals": ([_h, ctypes.POINTER(_vp)], ctypes.c_int),
     "csrk_copy_device_vals": ([_h, _vp, _vp], ctypes.c_int),
@@ -263,6 +264,22 @@ def csrk_copy_structure(h: int) -> dict:
     _check(lib().csrk_copy_structure(h, _ptr(out["perm"], _i32p), _ptr(out["row_ptr"], _i32p),
                                      _ptr(out["col_idx"], _i32p), _ptr(out["vals"], _f64p), _ptr(out["vmap"], _i64p),
                                      _ptr(out["sr_ptr"], _i32p), _ptr(out["ssr_ptr"], _i32p)), "csrk_copy_structure")
+    return out
+
+
+def csrk_copy_union(h: int):
+    """The union-pattern index of a nonsymmetric handle as numpy arrays, or None when it has none."""
+    nu = ctypes.c_int64(0)
+    _check(lib().csrk_copy_union(h, ctypes.byref(nu), None, None, None, None, None), "csrk_copy_union")
+    if nu.value == 0:
+        return None
+    info = csrk_get_info(h)
+    out = {"u_col": np.empty(nu.value, np.int32), "u_src": np.empty(nu.value, np.int32),
+           "erow_ptr": np.empty(info["n"] + 1, np.int32), "sr_begin": np.empty(info["nsr"], np.int32),
+           "sr_end": np.empty(info["nsr"], np.int32)}
+    ptr = lambda a: a.ctypes.data_as(_vp)  # noqa: E731
+    _check(lib().csrk_copy_union(h, ctypes.byref(nu), ptr(out["u_col"]), ptr(out["u_src"]), ptr(out["erow_ptr"]),
+                                 ptr(out["sr_begin"]), ptr(out["sr_end"])), "csrk_copy_union")
     return out
 
 

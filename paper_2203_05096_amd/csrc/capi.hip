@@ -30,6 +30,7 @@ struct csrk_matrix {
     csrk::Stats in_stats, out_stats;
     int32_t max_sr_nnz = 0, max_ssr_rows = 0;
     csrk::Transposed trans;  // index structure of A'^T for the adjoint
+    csrk::UnionIndex uni;    // union pattern A' + A'^T of a nonsymmetric A' (ok == false otherwise)
     // device side
     bool on_device = false;
     csrk_dtype store = CSRK_F64;
@@ -172,6 +173,8 @@ void finish_host(csrk_matrix *h, const int32_t *row_ptr, const int32_t *col_idx,
     for (size_t t = 0; t + 1 < h->ssr_ptr.size(); ++t)
         h->max_ssr_rows = std::max(h->max_ssr_rows, h->sr_ptr[h->ssr_ptr[t + 1]] - h->sr_ptr[h->ssr_ptr[t]]);
     h->trans = csrk::transpose_index(h->n, h->row_ptr, h->col_idx);
+    h->uni = csrk::union_index(h->n, h->row_ptr, h->col_idx, h->sr_ptr, h->trans, csrk::dev::kUnionRows,
+                               csrk::dev::kUnionWindow);
     h->max_row_any = 0;
     for (int32_t i = 0; i < h->n; ++i) {
         h->max_row_any = std::max(h->max_row_any, h->row_ptr[size_t(i) + 1] - h->row_ptr[size_t(i)]);
@@ -498,9 +501,7 @@ csrk_status csrk_upload(csrk_handle h, csrk_dtype store) {
                         }
                     h->d_srec_t = upload_array(rec, "transposed super-row records");
                     // the union pattern, when every super-row fits one staging window
-                    const csrk::UnionIndex un =
-                        csrk::union_index(h->n, h->row_ptr, h->col_idx, h->sr_ptr, h->trans, csrk::dev::kUnionRows,
-                                          csrk::dev::kUnionWindow);
+                    const csrk::UnionIndex &un = h->uni;
                     if (un.ok) {
                         for (size_t t = 0; t < nssr; ++t)
                             for (int32_t s = h->ssr_ptr[t]; s < h->ssr_ptr[t + 1]; ++s) {
@@ -636,6 +637,25 @@ csrk_status csrk_level_ptr(csrk_handle h, int32_t level, int32_t *count, int32_t
             level == 1 ? h->sr_ptr : level == 2 ? h->ssr_ptr : h->upper_ptr[size_t(level) - 3];
         *count = static_cast<int32_t>(v.size()) - 1;
         if (out) std::memcpy(out, v.data(), v.size() * sizeof(int32_t));
+        return CSRK_OK;
+    });
+}
+
+csrk_status csrk_copy_union(csrk_handle h, int64_t *nu, int32_t *u_col, int32_t *u_src, int32_t *erow_ptr,
+                            int32_t *sr_begin, int32_t *sr_end) {
+    return guard([&] {
+        if (!h || !nu) throw Error{CSRK_ERR_ARG, "null handle or nu"};
+        const csrk::UnionIndex &u = h->uni;
+        *nu = u.ok ? static_cast<int64_t>(u.u_col.size()) : 0;
+        if (!u.ok) return CSRK_OK;
+        auto cp = [](int32_t *dst, const std::vector<int32_t> &v) {
+            if (dst && !v.empty()) std::memcpy(dst, v.data(), v.size() * sizeof(int32_t));
+        };
+        cp(u_col, u.u_col);
+        cp(u_src, u.u_src);
+        cp(erow_ptr, u.erow_ptr);
+        cp(sr_begin, u.sr_begin);
+        cp(sr_end, u.sr_end);
         return CSRK_OK;
     });
 }

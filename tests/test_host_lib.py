@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from gen import laplacian, random_sparse, workload_c1, workload_c2
+from gen import laplacian, random_sparse, workload_c1, workload_c2, workload_c4
 from oracle import bandk as OB
 from oracle import stats as OS
 from oracle import tune as OT
@@ -189,6 +189,80 @@ def test_general_k_irregular_split_keeps_upper_levels():
         rows_ref = sr0[ssr0[up]]
         rows_lib = s["sr_ptr"][s["ssr_ptr"][lib_up]]
         assert np.array_equal(rows_ref, rows_lib)
+    finally:
+        C.csrk_destroy(h)
+
+
+def _union_reference(s):
+    """The union-pattern layout built directly from its description (csrk_copy_union in include/csrk.h)."""
+    rp, ci, srp = s["row_ptr"].astype(np.int64), s["col_idx"].astype(np.int64), s["sr_ptr"].astype(np.int64)
+    n = len(rp) - 1
+    pos = {}
+    for i in range(n):
+        for k in range(rp[i], rp[i + 1]):
+            pos[(i, int(ci[k]))] = k
+    extras = [[] for _ in range(n)]  # row i: columns j with (j, i) in A' and (i, j) not
+    for (i, j), k in pos.items():
+        if (j, i) not in pos:
+            extras[j].append((i, k))
+    erow = np.zeros(n + 1, np.int64)
+    for i in range(n):
+        extras[i].sort()
+        erow[i + 1] = erow[i] + len(extras[i])
+    u_col, u_src, begin, end = [], [], [], []
+    for t in range(len(srp) - 1):
+        r0, r1 = srp[t], srp[t + 1]
+        if r1 - r0 > 64 or (rp[r1] - rp[r0]) + (erow[r1] - erow[r0]) > 504:
+            return None
+        begin.append(len(u_col))
+        for i in range(r0, r1):
+            for k in range(rp[i], rp[i + 1]):
+                u_col.append(int(ci[k]))
+                u_src.append(pos.get((int(ci[k]), i), -1))
+        for i in range(r0, r1):
+            for j, k in extras[i]:
+                u_col.append(j)
+                u_src.append(k)
+        end.append(len(u_col))
+        while (len(u_col) - begin[-1] - (rp[r1] - rp[r0])) % 8:
+            u_col.append(int(r0))
+            u_src.append(-1)
+    return {"u_col": u_col, "u_src": u_src, "erow_ptr": erow.tolist(), "sr_begin": begin, "sr_end": end}
+
+
+@pytest.mark.parametrize("seed,srs,ssrs,sym", [(1, 8, 2, False), (2, 19, 4, False), (3, 48, 2, False),
+                                               (4, 100, 2, False), (5, 16, 2, True)])
+def test_union_index_layout(seed, srs, ssrs, sym):
+    """The union pattern of a nonsymmetric A' (one-pass adjoint): every array as the layout describes it, or no
+    union when the pattern is symmetric or a super-row does not fit one window."""
+    A = random_sparse(700, 4.0, seed=seed, empty_row_frac=0.1, symmetric_pattern=sym)
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, _params(srs, ssrs))
+    try:
+        s = C.csrk_copy_structure(h)
+        got = C.csrk_copy_union(h)
+    finally:
+        C.csrk_destroy(h)
+    ref = None if sym else _union_reference(s)
+    if ref is None:
+        assert got is None
+        return
+    assert got is not None
+    for key in ("u_col", "u_src", "erow_ptr", "sr_begin", "sr_end"):
+        assert got[key].tolist() == ref[key], key
+    # the A' part of super-row t sits at a multiple-of-8 offset from its A' positions
+    off = got["sr_begin"] - s["row_ptr"][s["sr_ptr"][:-1]]
+    assert np.all(off % 8 == 0) and np.all(np.diff(off) >= 0)
+
+
+def test_union_index_c4_fits():
+    """The 2D 9-point matrix with 10% of its off-diagonals dropped gets a union at its tuned sizes."""
+    A = workload_c4()["A"]
+    h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, C.csrk_tune(A.n, A.nnz, "mi355x"))
+    try:
+        u = C.csrk_copy_union(h)
+        assert u is not None
+        extras, nsr = int(u["erow_ptr"][-1]), len(u["sr_begin"])
+        assert A.nnz + extras <= len(u["u_col"]) <= A.nnz + extras + 7 * nsr  # padding: < 8 per super-row
     finally:
         C.csrk_destroy(h)
 
