@@ -148,6 +148,25 @@ def test_c4_full_adjoint_and_finite_differences():
         assert abs(fd - gv[k]) <= (2.0 ** -24 + fd_err) * abs(g[rows[k]] * x[A.col_idx[k]])
 
 
+@pytest.mark.parametrize("store", ["bf16", "f64"])
+def test_c4_full_union_adjoint_other_precisions(store):
+    """The full-size nonsymmetric c4 matrix through the union pass in BF16 and FP64 storage."""
+    w = workload_c4()
+    A, x, g = w["A"], w["x"], w["g"]
+    if store == "bf16":
+        A.vals = OP.stored_values(A.vals, store)
+    p = C.csrk_tune(A.n, A.nnz, "mi355x")
+    say("c4 union adjoint", store, p)
+    M = _build(A, store, p)
+    assert M.info["adjoint_union"] == 1
+    gx, gv = _adjoint(M, x, g)
+    ref_gv = OA.grad_vals(A.row_ptr, A.col_idx, x, g)
+    if store != "f64":
+        ref_gv = ref_gv.astype(np.float32).astype(np.float64)
+    assert np.array_equal(gv, ref_gv)
+    _check_grad_x(gx, A, g, "f32" if store != "f64" else "f64", False, f"c4 {store}")
+
+
 def test_autograd_gradcheck_f64():
     A = random_sparse(40, 4.0, seed=8, empty_row_frac=0.1)
     M = _build(A, "f64", params(5, 2))

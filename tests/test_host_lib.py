@@ -267,6 +267,21 @@ def test_union_index_c4_fits():
         C.csrk_destroy(h)
 
 
+def test_level_ptr_k2_and_k3():
+    """k = 2 and 3 have levels 1 and 2 (for k = 2 level 2 is the launch grouping of the super-rows)."""
+    A = random_sparse(400, 4.0, seed=21)
+    for k in (2, 3):
+        h = C.csrk_build_host(A.row_ptr, A.col_idx, A.vals, _params(7, 3, "bandk", k))
+        try:
+            s = C.csrk_copy_structure(h)
+            assert np.array_equal(C.csrk_level_ptr(h, 1), s["sr_ptr"])
+            assert np.array_equal(C.csrk_level_ptr(h, 2), s["ssr_ptr"])
+            with pytest.raises(C.CsrkError):
+                C.csrk_level_ptr(h, 3)
+        finally:
+            C.csrk_destroy(h)
+
+
 def test_from_groups_rejects_k4():
     rp, ci = _path(8)
     with pytest.raises(C.CsrkError):
