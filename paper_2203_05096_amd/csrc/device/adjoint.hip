@@ -76,7 +76,9 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     const int32_t *__restrict__ cols, const int32_t *__restrict__ t_row_ptr, const int32_t *__restrict__ t_col,
     const int32_t *__restrict__ t_src, const VT *__restrict__ valsT, const typename Store<VT>::X *__restrict__ x,
     const typename Store<VT>::X *__restrict__ g, typename Store<VT>::X *__restrict__ gx,
-    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, int sym, XcdSplit split) {
+    typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs, int sym, XcdSplit split,
+    const SrRec *__restrict__ srec_u, const int32_t *__restrict__ erow_ptr, const int32_t *__restrict__ u_col,
+    const int32_t *__restrict__ u_src, const VT *__restrict__ u_vals, int64_t nu) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
@@ -91,6 +93,12 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
             if (sym != 0 && gx && gv) {
                 sr_adjoint_fused_mrhs_rec<VT, RL, VX, IND>(rec, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, nrhs,
                                                            lds, lane);
+                continue;
+            }
+            if (srec_u && gx && gv) {  // nonsymmetric: one pass over the union pattern
+                mrhs_adjoint_union_window<VT, RL, VX, IND>(rec, srec_u[int64_t(t) * stride + w], row_ptr, erow_ptr,
+                                                           u_col, u_src, IND ? valsT : u_vals, x, g, gx, gv, nu,
+                                                           nrhs, lds, lane);
                 continue;
             }
         }
@@ -160,11 +168,13 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                 constexpr int VX = decltype(vc)::value;
                 return by_lanes(rhs_lanes(nrhs, VX), [&](auto rc) -> hipError_t {
                     constexpr int RL = decltype(rc)::value;
+                    // with caller values the union pass reaches them through u_src (valsT is then the caller's)
                     hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.split_adj.width * kXcds),
                                        dim3(block), size_t(s.waves) * kMrhsLds, st, a.srec, a.srec_stride, a.row_ptr,
                                        a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
                                        static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
-                                       nrhs, int(a.sym), a.split_adj);
+                                       nrhs, int(a.sym), a.split_adj, a.sym ? nullptr : a.srec_u, a.erow_ptr, a.u_col,
+                                       a.u_src, static_cast<const VT *>(a.u_vals), a.nu);
                     return hipGetLastError();
                 });
             });

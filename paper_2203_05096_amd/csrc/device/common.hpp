@@ -1883,6 +1883,171 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs_rec(const SrRec &rec, cons
                                                nnz, nrhs, lds, lane);
 }
 
+// Both gradients of one super-row of a nonsymmetric pattern, several
+// right-hand sides, in one pass over its union-pattern range (the
+// multi-column form of sr_adjoint_union_rec): per row, RL lanes x VX columns
+// walk the row's A' part, gathering the x and g slices of every column j
+// (grad_vals[k] = sum_c g_ic x_jc, grad_x[i] += a'_ji g_j), then its extras,
+// gathering g only.  `ra` / `ru`: the super-row's records in A' and in U; the
+// host builds U only when every super-row has at most 64 rows and fits one
+// window.  FP32 accumulation only.
+template <typename VT, int RL, int VX, bool IND>
+__device__ __forceinline__ void mrhs_adjoint_union_window(const SrRec &ra, const SrRec &ru,
+                                                          const int32_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ erow_ptr,
+                                                          const int32_t *__restrict__ ucols,
+                                                          const int32_t *__restrict__ usrc, const VT *__restrict__ vals,
+                                                          const typename Store<VT>::X *__restrict__ x,
+                                                          const typename Store<VT>::X *__restrict__ g,
+                                                          typename Store<VT>::X *__restrict__ gx,
+                                                          typename Store<VT>::A *__restrict__ gv, int64_t nu,
+                                                          int nrhs, unsigned char *__restrict__ lds, int lane) {
+    using A = typename Store<VT>::A;
+    using X = typename Store<VT>::X;
+    static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
+    constexpr int V = Store<VT>::V;
+    constexpr int CAP = kStageEntries;
+    constexpr int U = CAP / (kWave * V);
+    constexpr int RPP = kWave / RL;
+    constexpr int CPP = RL * VX;
+    constexpr int VA = 16 / int(sizeof(A));
+    typedef A AV __attribute__((ext_vector_type(VA)));
+    A *sval = reinterpret_cast<A *>(lds);
+    int32_t *scol = reinterpret_cast<int32_t *>(lds + CAP * sizeof(A));
+    A *sgv = reinterpret_cast<A *>(lds + CAP * (sizeof(A) + sizeof(int32_t)));
+    const int32_t r0 = ra.r0;
+    const int nrows = ra.r1 - ra.r0;
+    const int32_t cs = ru.e0, ce = ru.e1;  // U range (no padding)
+    const int32_t e = ru.e0 - ra.e0;       // U position of A' entry k is k + e (e % 8 == 0)
+    const int32_t ca = ra.e1 + e;          // end of the A' part
+    const int q = lane % RL;
+    const int rsub = lane / RL;
+    const int32_t off = cs - (cs & ~(V - 1));  // LDS index of entry cs
+    const int64_t base = int64_t(cs & ~(V - 1)) + int64_t(lane) * V;
+    // row ends in U coordinates: of the A' part (a_end) and of the extras (x_end)
+    const int32_t eb = uniform(erow_ptr[r0]);
+    const int32_t a_end = lane < nrows ? row_ptr[r0 + lane + 1] + e : 0;
+    const int32_t x_end = lane < nrows ? ca + (erow_ptr[r0 + lane + 1] - eb) : 0;
+    A v[U][V];
+    int32_t c[U][V];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t pos = base + int64_t(u) * kWave * V;
+        if (pos < ce) {
+            load_vec<VT, IND>(vals, ucols, usrc, pos, nu, v[u], c[u]);
+        } else {
+#pragma unroll
+            for (int t = 0; t < V; ++t) {
+                v[u][t] = A(0);
+                c[u][t] = 0;
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int t = 0; t < V; ++t) {
+            sval[u * kWave * V + lane * V + t] = v[u][t];
+            scol[u * kWave * V + lane * V + t] = c[u][t];
+        }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int b = 0; b < nrows; b += RPP) {
+        const int rr = b + rsub;
+        const bool act = rr < nrows;
+        const int src = act ? rr : 0, prv = (act && rr > 0) ? rr - 1 : 0;
+        const int32_t a1 = __shfl(a_end, src) - cs, a0p = __shfl(a_end, prv) - cs;
+        const int32_t x1 = __shfl(x_end, src) - cs, x0p = __shfl(x_end, prv) - cs;
+        const int32_t a0 = rr > 0 ? a0p : 0;
+        const int32_t x0 = rr > 0 ? x0p : ca - cs;
+        if (!act) continue;  // a row's RL lanes are active or idle together
+        for (int cb = 0; cb < nrhs; cb += CPP) {
+            const int col0 = cb + q * VX;
+            const bool cok = col0 < nrhs;
+            X gi[VX];
+            A acc[VX];
+#pragma unroll
+            for (int t = 0; t < VX; ++t) {
+                gi[t] = X(0);
+                acc[t] = A(0);
+            }
+            if (cok) load_cols<X, VX>(g + int64_t(r0 + rr) * nrhs + col0, gi);
+            // the A' part, four entries at a time: x and g slices all requested before any is used
+            for (int32_t k0 = a0; k0 < a1; k0 += 4) {
+                X xv[4][VX], gj[4][VX];
+                A a[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = cok && k0 + t < a1;
+                    a[t] = ok ? sval[off + k0 + t] : A(0);
+                    if (ok) {
+                        const int64_t j = scol[off + k0 + t];
+                        load_cols<X, VX>(x + j * nrhs + col0, xv[t]);
+                        load_cols<X, VX>(g + j * nrhs + col0, gj[t]);
+                    } else {
+#pragma unroll
+                        for (int z = 0; z < VX; ++z) xv[t][z] = gj[t][z] = X(0);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    A p = 0;
+#pragma unroll
+                    for (int z = 0; z < VX; ++z) {
+                        p += A(gi[z]) * A(xv[t][z]);
+                        acc[z] += a[t] * A(gj[t][z]);
+                    }
+                    p = group_sum<RL>(p);
+                    if (q == 0 && k0 + t < a1) sgv[k0 + t] = cb == 0 ? p : sgv[k0 + t] + p;
+                }
+            }
+            // the extras: g slices only
+            for (int32_t k0 = x0; k0 < x1; k0 += 4) {
+                X gj[4][VX];
+                A a[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const bool ok = cok && k0 + t < x1;
+                    a[t] = ok ? sval[off + k0 + t] : A(0);
+                    if (ok) {
+                        load_cols<X, VX>(g + int64_t(scol[off + k0 + t]) * nrhs + col0, gj[t]);
+                    } else {
+#pragma unroll
+                        for (int z = 0; z < VX; ++z) gj[t][z] = X(0);
+                    }
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int z = 0; z < VX; ++z) acc[z] += a[t] * A(gj[t][z]);
+            }
+            if (cok) {
+                X out[VX];
+#pragma unroll
+                for (int t = 0; t < VX; ++t) out[t] = X(acc[t]);
+                store_cols<X, VX>(gx + int64_t(r0 + rr) * nrhs + col0, out);
+            }
+        }
+    }
+    wave_lds_sync();
+    // grad_vals of the A' part, from LDS, at A' positions (U position - e)
+    for (int64_t pos = int64_t(cs & ~(VA - 1)) + int64_t(lane) * VA; pos < ca; pos += int64_t(kWave) * VA) {
+        if (pos >= cs && pos + VA <= ca) {
+            AV ov;
+#pragma unroll
+            for (int t = 0; t < VA; ++t) ov[t] = sgv[pos + t - cs];
+            *reinterpret_cast<AV *>(gv + (pos - e)) = ov;
+        } else {
+#pragma unroll
+            for (int t = 0; t < VA; ++t) {
+                const int64_t k = pos + t;
+                if (k >= cs && k < ca) gv[k - e] = sgv[k - cs];
+            }
+        }
+    }
+    wave_lds_sync();
+}
+
 // Both gradients of one super-row, several right-hand sides (RL lanes x VX
 // columns per row): one fused pass for a symmetric pattern with both outputs
 // and FP32 accumulation, else grad_vals and then grad_x over A'^T.

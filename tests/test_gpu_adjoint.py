@@ -281,6 +281,30 @@ def test_adjoint_nonsymmetric_union_and_two_phase(store, explicit_vals, srs):
     assert torch.equal(gv2, gv)
 
 
+@pytest.mark.parametrize("nrhs", [4, 8])
+def test_adjoint_multi_rhs_union_and_two_phase(nrhs):
+    """A nonsymmetric pattern with blocks of right-hand sides: the union pass (SRS 21) and the two-phase walk
+    (SRS 200, super-rows past 64 rows) against the oracle, bitwise equal grad_vals."""
+    A = random_sparse(3000, 6.0, seed=70 + nrhs, empty_row_frac=0.05)
+    A.vals = OP.stored_values(A.vals, "f32")
+    rng = np.random.default_rng(71)
+    X = rng.uniform(-1, 1, (A.n, nrhs)).astype(np.float32).astype(np.float64)
+    G = rng.uniform(-1, 1, (A.n, nrhs)).astype(np.float32).astype(np.float64)
+    ref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, G)
+    scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(G))
+    colcount = np.maximum(np.bincount(A.col_idx, minlength=A.n), 1)[:, None]
+    refv = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    scalev = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+    for srs, union in ((21, 1), (200, 0)):
+        say("adjoint mrhs union/two-phase", nrhs, srs)
+        M = _build(A, "f32", params(srs, 2, lanes=2, waves=2))
+        assert M.info["adjoint_union"] == union
+        gx, gv = _adjoint(M, X, G)
+        assert np.all(np.abs(gx - ref) <= OP.gamma(colcount, 2.0 ** -24) * scale), f"grad_x, SRS {srs}"
+        assert np.all(np.abs(gv - refv) <= OP.gamma(nrhs, 2.0 ** -24) * scalev), f"grad_vals, SRS {srs}"
+        M.close()
+
+
 def test_adjoint_deterministic():
     A = random_sparse(5000, 8.0, seed=31, symmetric_pattern=True)
     M = _build(A, "f64", params(32, 4))
@@ -374,8 +398,8 @@ def test_c2_full_adjoint_random_vectors_at_tuned_shape():
 @pytest.mark.parametrize("explicit_vals", [False, True])
 def test_adjoint_multi_rhs_precisions(nrhs, store, symmetric, explicit_vals):
     """Blocks of right-hand sides in every storage type, symmetric (one fused pass when both outputs are wanted
-    and the accumulation is FP32) and nonsymmetric patterns (grad_vals, then A'^T g), with the handle's values
-    or values passed in."""
+    and the accumulation is FP32) and nonsymmetric patterns (one pass over the union pattern with FP32
+    accumulation, else grad_vals then A'^T g), with the handle's values or values passed in."""
     A = random_sparse(2500, 7.0, seed=40 + nrhs, empty_row_frac=0.05, symmetric_pattern=symmetric)
     A.vals = OP.stored_values(A.vals, store)
     rng = np.random.default_rng(41 + nrhs)
@@ -385,6 +409,7 @@ def test_adjoint_multi_rhs_precisions(nrhs, store, symmetric, explicit_vals):
         X, G = X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
     say("adjoint mrhs", nrhs, store, symmetric, explicit_vals)
     M = _build(A, store, params(21, 4))
+    assert M.info["adjoint_union"] == (0 if symmetric else 1)
     s = M.structure()
     perm, vmap = s["perm"], s["vmap"]
     dt = VEC[store]
