@@ -62,6 +62,7 @@ struct csrk_batch_s {
     int32_t nitems = 0, max_n = 0;
     int2 *d_items = nullptr;
     csrk::dev::SrRec *d_brec = nullptr;  // per item, brec_stride super-row records of its SSR
+    csrk::dev::SrRec *d_brec_u = nullptr;  // the same slots' union-pattern records (matrices that have one)
     int32_t brec_stride = 1;
     // Descriptor tables on the device (forward, adjoint) and the host copies
     // they were written from; a call re-uploads only when its pointers change.
@@ -982,6 +983,18 @@ csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_ba
                 }
             }
             bt->d_brec = upload_array(brec, "batch super-row records");
+            // the union-pattern ranges of the same super-rows (nonsymmetric matrices that have a union index)
+            for (size_t it = 0; it < items.size(); ++it) {
+                const csrk_matrix *h = handles[items[it].x];
+                if (!h->d_srec_u) continue;
+                const int32_t t = items[it].y;
+                for (int32_t s = h->ssr_ptr[size_t(t)]; s < h->ssr_ptr[size_t(t) + 1]; ++s) {
+                    auto &r = brec[it * size_t(bt->brec_stride) + size_t(s - h->ssr_ptr[size_t(t)])];
+                    r.e0 = h->uni.sr_begin[size_t(s)];
+                    r.e1 = h->uni.sr_end[size_t(s)];
+                }
+            }
+            bt->d_brec_u = upload_array(brec, "batch union super-row records");
             for (int k = 0; k < 2; ++k)
                 hip_check(hipMalloc(&bt->d_descs[k], sizeof(csrk::dev::MatDesc) * size_t(count)), "batch descriptors");
             // Batch-wide kernel shape: the first handle's lanes/waves, which
@@ -993,6 +1006,7 @@ csrk_status csrk_batch_create(const csrk_handle *handles, int32_t count, csrk_ba
         } catch (...) {
             if (bt->d_items) (void)hipFree(bt->d_items);
             if (bt->d_brec) (void)hipFree(bt->d_brec);
+            if (bt->d_brec_u) (void)hipFree(bt->d_brec_u);
             for (auto *p : bt->d_descs)
                 if (p) (void)hipFree(p);
             delete bt;
@@ -1031,6 +1045,14 @@ csrk::dev::MatDesc *upload_descs(csrk_batch b, int which, const void *const *val
         m.n = h->n;
         m.nssr = static_cast<int32_t>(h->ssr_ptr.size()) - 1;
         m.sym = h->trans.symmetric ? 1 : 0;
+        if (which == 1 && h->d_srec_u) {
+            m.uni = 1;
+            m.u_col = a.u_col;
+            m.u_src = a.u_src;
+            m.erow_ptr = a.erow_ptr;
+            m.u_vals = a.u_vals;
+            m.nu = a.nu;
+        }
         if (which == 1) {
             // adjoint: caller values (CSR-k order, reached through t_src) when any
             // are given, otherwise the handles' transposed copies
@@ -1117,7 +1139,8 @@ csrk_status csrk_batch_spmv_adjoint(csrk_batch b, const void *const *vals, const
         const bool ind = vals && std::any_of(vals, vals + b->handles.size(), [](const void *p) { return p != nullptr; });
         const bool vec = all_aligned16({x, g, reinterpret_cast<const void *const *>(grad_x)}, b->handles.size());
         const bool both = grad_x && grad_vals;
-        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->d_brec, b->brec_stride, b->nitems, b->store, nrhs,
+        hip_check(csrk::dev::batch_adjoint(descs, b->d_items, b->d_brec, b->d_brec_u, b->brec_stride, b->nitems,
+                                           b->store, nrhs,
                                            b->shape,
                                            batch_grid(b, nrhs, true, ind, vec, both), ind, vec, b->all_sym, both, st),
                   "csrk_batch_spmv_adjoint launch");
@@ -1163,6 +1186,7 @@ csrk_status csrk_batch_destroy(csrk_batch b) {
         DeviceScope ds(b->device);
         if (b->d_items) (void)hipFree(b->d_items);
         if (b->d_brec) (void)hipFree(b->d_brec);
+        if (b->d_brec_u) (void)hipFree(b->d_brec_u);
         for (auto *p : b->d_descs)
             if (p) (void)hipFree(p);
         delete b;

@@ -57,7 +57,8 @@ enum BatchAdjPath { kAdjSingle = 0, kAdjMrhsFused = 1, kAdjMrhsAny = 2 };
 
 template <typename VT, int L, int VX, bool IND, int PATH>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
-                                                        const SrRec *__restrict__ brec, int32_t stride,
+                                                        const SrRec *__restrict__ brec,
+                                                        const SrRec *__restrict__ brec_u, int32_t stride,
                                                         int32_t nitems, int nrhs) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
@@ -85,13 +86,34 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
             const SrRec rec = brec[int64_t(it) * stride + w];
             if (rec.r0 >= rec.r1) break;
             const int32_t r0 = rec.r0, r1 = rec.r1;
+            // a nonsymmetric matrix with a union-pattern index: both gradients in one pass over it (values
+            // reached through u_src when the caller passes them)
+            const bool uni = d.uni != 0 && gx && gv;
             if constexpr (PATH == kAdjSingle) {
+                if (uni) {
+                    sr_adjoint_union_rec<VT, L, IND>(rec, brec_u[int64_t(it) * stride + w], row_ptr,
+                                                     global_ptr(d.erow_ptr), global_ptr(d.u_col),
+                                                     global_ptr(d.u_src),
+                                                     IND ? vals : global_ptr(static_cast<const VT *>(d.u_vals)), x, g,
+                                                     gx, gv, d.nu, lds, lane);
+                    continue;
+                }
                 sr_adjoint<VT, L, IND>(r0, r1, row_ptr, col_idx, t_row_ptr, t_col, t_src, vals, x, g, gx, gv, d.nnz,
                                        d.sym != 0, lds, lane, false);
             } else if constexpr (PATH == kAdjMrhsFused) {
                 sr_adjoint_fused_mrhs_rec<VT, L, VX, IND>(rec, row_ptr, col_idx, t_src, vals, x, g, gx, gv, d.nnz,
                                                           nrhs, lds, lane);
             } else {
+                if constexpr (sizeof(A) == 4) {
+                    if (uni) {
+                        mrhs_adjoint_union_window<VT, L, VX, IND>(
+                            rec, brec_u[int64_t(it) * stride + w], row_ptr, global_ptr(d.erow_ptr),
+                            global_ptr(d.u_col), global_ptr(d.u_src),
+                            IND ? vals : global_ptr(static_cast<const VT *>(d.u_vals)), x, g, gx, gv, d.nu, nrhs, lds,
+                            lane);
+                        continue;
+                    }
+                }
                 sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, row_ptr, col_idx, t_row_ptr, t_col, t_src, vals, x, g, gx, gv,
                                                 d.nnz, nrhs, d.sym != 0, lds, lane);
             }
@@ -168,9 +190,9 @@ hipError_t by_adj_variant(bool ind, int path, F &&f) {
     return ind ? with_path(std::true_type{}) : with_path(std::false_type{});
 }
 
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
-                         csrk_dtype store, int nrhs, Shape s, int grid, bool ind, bool vec, bool all_sym, bool both,
-                         hipStream_t st) {
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, const SrRec *brec_u,
+                         int32_t stride, int32_t nitems, csrk_dtype store, int nrhs, Shape s, int grid, bool ind,
+                         bool vec, bool all_sym, bool both, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
     const size_t lds = size_t(s.waves) * kBatchLds;
@@ -185,7 +207,7 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *b
                 return hipErrorInvalidValue;  // never chosen (see adj_variant_exists)
             } else {
                 hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, IND, PATH>), dim3(grid), dim3(block), lds, st, descs,
-                                   items, brec, stride, nitems, nrhs);
+                                   items, brec, brec_u, stride, nitems, nrhs);
                 return hipGetLastError();
             }
         });

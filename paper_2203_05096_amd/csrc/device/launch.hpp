@@ -106,6 +106,12 @@ struct MatDesc {
     int32_t n;
     int32_t nssr;
     int32_t sym;
+    int32_t uni;  // the matrix has a union-pattern index (Arrays::u_col ...): the adjoint takes one pass
+    const int32_t *u_col;
+    const int32_t *u_src;
+    const int32_t *erow_ptr;
+    const void *u_vals;
+    int64_t nu;
 };
 
 // Kernel-shape knobs: lanes per row in the reduction, wavefronts per workgroup.
@@ -144,9 +150,11 @@ hipError_t batch_forward(const MatDesc *descs, const int2 *items, const SrRec *b
 // `all_sym`: every matrix of the batch has a symmetric pattern; `both`: both
 // gradients are wanted (then a multi-right-hand-side launch with FP32
 // accumulation runs the fused-only kernel).
-hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, int32_t stride, int32_t nitems,
-                         csrk_dtype store, int nrhs, Shape s, int grid, bool ind, bool vec, bool all_sym, bool both,
-                         hipStream_t st);
+// `brec_u`: per item, the same slots' union-pattern records (for matrices
+// with uni set; other slots repeat brec).
+hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *brec, const SrRec *brec_u,
+                         int32_t stride, int32_t nitems, csrk_dtype store, int nrhs, Shape s, int grid, bool ind,
+                         bool vec, bool all_sym, bool both, hipStream_t st);
 
 // Workgroups per CU the batched kernels can keep resident (for sizing the grid).
 int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adjoint, bool ind, bool vec, bool all_sym,
