@@ -305,6 +305,58 @@ def test_adjoint_multi_rhs_union_and_two_phase(nrhs):
         M.close()
 
 
+def _structured_nonsymmetric(kind, n, seed):
+    """Hand-built nonsymmetric patterns: upper bidiagonal (every row but the first gets one extra in the union,
+    its lower neighbour), a dense lower triangle (union rows are full), and an upper bidiagonal with empty rows
+    (rows reached only through their extras)."""
+    from gen import CsrInput
+    rows = []
+    for i in range(n):
+        if kind == "bidiag":
+            rows.append([j for j in (i, i + 1) if j < n])
+        elif kind == "lower":
+            rows.append(list(range(i + 1)))
+        else:  # "holes": every third row stored empty
+            rows.append([] if i % 3 == 1 else [j for j in (i, i + 1) if j < n])
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.array([j for r in rows for j in r], dtype=np.int32)
+    vals = np.random.default_rng(seed).uniform(-1, 1, len(ci))
+    return CsrInput(kind, n, rp, ci, vals, {"seed": seed})
+
+
+@pytest.mark.parametrize("kind,n", [("bidiag", 1), ("bidiag", 2), ("bidiag", 65), ("bidiag", 300), ("lower", 40),
+                                    ("holes", 200)])
+@pytest.mark.parametrize("nrhs", [1, 3])
+def test_adjoint_union_structured(kind, n, nrhs):
+    """The union pass on hand-built nonsymmetric patterns, FP64 (one column) and FP32 (blocks of three)."""
+    A = _structured_nonsymmetric(kind, n, seed=n)
+    store = "f64" if nrhs == 1 else "f32"
+    if store == "f32":
+        A.vals = OP.stored_values(A.vals, store)
+    rng = np.random.default_rng(n + 1)
+    shp = (A.n,) if nrhs == 1 else (A.n, nrhs)
+    X, G = rng.uniform(-1, 1, shp), rng.uniform(-1, 1, shp)
+    if store == "f32":
+        X, G = X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
+    say("adjoint union structured", kind, n, nrhs)
+    M = _build(A, store, params(8, 2, lanes=2, waves=2))
+    sym = bool(n == 1)  # a single diagonal entry is its own mirror
+    assert M.info["adjoint_union"] == (0 if sym else 1)
+    gx, gv = _adjoint(M, X, G)
+    ref = OA.grad_x(A.row_ptr, A.col_idx, A.vals, G)
+    scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(G))
+    cc = np.maximum(np.bincount(A.col_idx, minlength=A.n), 1)
+    cc = cc if nrhs == 1 else cc[:, None]
+    beta = 1e-12 if store == "f64" else OP.gamma(cc, 2.0 ** -24)
+    assert np.all(np.abs(gx - ref) <= beta * scale)
+    refv = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    if nrhs == 1:
+        assert np.array_equal(gv, refv)
+    else:
+        scalev = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+        assert np.all(np.abs(gv - refv) <= OP.gamma(nrhs, 2.0 ** -24) * scalev)
+
+
 def test_adjoint_deterministic():
     A = random_sparse(5000, 8.0, seed=31, symmetric_pattern=True)
     M = _build(A, "f64", params(32, 4))

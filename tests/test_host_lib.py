@@ -254,6 +254,33 @@ def test_union_index_layout(seed, srs, ssrs, sym):
     assert np.all(off % 8 == 0) and np.all(np.diff(off) >= 0)
 
 
+@pytest.mark.parametrize("kind", ["bidiag", "lower", "holes"])
+def test_union_index_structured(kind):
+    """Hand-built nonsymmetric patterns (upper bidiagonal, dense lower triangle, rows reached only through
+    their extras): the union layout exactly as described."""
+    n = 40 if kind == "lower" else 150
+    rows = []
+    for i in range(n):
+        if kind == "bidiag":
+            rows.append([j for j in (i, i + 1) if j < n])
+        elif kind == "lower":
+            rows.append(list(range(i + 1)))
+        else:
+            rows.append([] if i % 3 == 1 else [j for j in (i, i + 1) if j < n])
+    rp = np.concatenate([[0], np.cumsum([len(r) for r in rows])]).astype(np.int32)
+    ci = np.array([j for r in rows for j in r], dtype=np.int32)
+    h = C.csrk_build_host(rp, ci, np.ones(len(ci)), _params(8, 2))
+    try:
+        s = C.csrk_copy_structure(h)
+        got = C.csrk_copy_union(h)
+    finally:
+        C.csrk_destroy(h)
+    ref = _union_reference(s)
+    assert ref is not None and got is not None
+    for key in ("u_col", "u_src", "erow_ptr", "sr_begin", "sr_end"):
+        assert got[key].tolist() == ref[key], key
+
+
 def test_union_index_c4_fits():
     """The 2D 9-point matrix with 10% of its off-diagonals dropped gets a union at its tuned sizes."""
     A = workload_c4()["A"]
