@@ -55,6 +55,12 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
 // two-phase per matrix).
 enum BatchAdjPath { kAdjSingle = 0, kAdjMrhsFused = 1, kAdjMrhsAny = 2 };
 
+// LDS bytes per wavefront of a batched adjoint path.
+template <typename VT, int PATH>
+__host__ __device__ constexpr int adj_lds() {
+    return PATH == kAdjSingle ? kBatchLds : mrhs_adjoint_lds<VT>();
+}
+
 template <typename VT, int L, int VX, bool IND, int PATH>
 __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restrict__ descs, const int2 *__restrict__ items,
                                                         const SrRec *__restrict__ brec,
@@ -66,7 +72,7 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    unsigned char *lds = smem + size_t(wave) * kBatchLds;
+    unsigned char *lds = smem + size_t(wave) * adj_lds<VT, PATH>();
     const int32_t b = xcd_contiguous(blockIdx.x, gridDim.x);
     const int32_t per = (nitems + gridDim.x - 1) / gridDim.x;
     const int32_t i0 = b * per, i1 = min(nitems, i0 + per);
@@ -157,20 +163,17 @@ hipError_t batch_forward(const MatDesc *descs, const int2 *items, const SrRec *b
 }
 
 // The adjoint path for a launch: several right-hand sides over symmetric
-// patterns with both outputs and FP32 accumulation take the fused-only
-// instantiation.
-inline int adj_path(csrk_dtype store, int nrhs, bool all_sym, bool both) {
+// patterns with both outputs take the fused-only instantiation.
+inline int adj_path(int nrhs, bool all_sym, bool both) {
     if (nrhs == 1) return kAdjSingle;
-    return (all_sym && both && store != CSRK_F64) ? kAdjMrhsFused : kAdjMrhsAny;
+    return (all_sym && both) ? kAdjMrhsFused : kAdjMrhsAny;
 }
 
 // Instantiations that a launch can choose: one right-hand side runs with one
-// column per lane, and the fused multi-column path stages 4-byte values
-// (FP32 accumulation) only.
+// column per lane.
 template <typename VT, int VX, int PATH>
 constexpr bool adj_variant_exists() {
     if constexpr (PATH == kAdjSingle) return VX == 1;
-    if constexpr (PATH == kAdjMrhsFused) return sizeof(typename Store<VT>::A) == 4;
     return true;
 }
 
@@ -195,8 +198,7 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *b
                          bool vec, bool all_sym, bool both, hipStream_t st) {
     if (nitems == 0) return hipSuccess;
     const int block = s.waves * kWave;
-    const size_t lds = size_t(s.waves) * kBatchLds;
-    const int path = adj_path(store, nrhs, all_sym, both);
+    const int path = adj_path(nrhs, all_sym, both);
     return by_batch_shape(store, nrhs, s, vec, [&](auto vt, auto vc, auto lc) -> hipError_t {
         using VT = decltype(vt);
         constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
@@ -206,6 +208,7 @@ hipError_t batch_adjoint(const MatDesc *descs, const int2 *items, const SrRec *b
             if constexpr (!adj_variant_exists<VT, VX, PATH>()) {
                 return hipErrorInvalidValue;  // never chosen (see adj_variant_exists)
             } else {
+                const size_t lds = size_t(s.waves) * adj_lds<VT, PATH>();
                 hipLaunchKernelGGL((k_batch_adjoint<VT, LL, VX, IND, PATH>), dim3(grid), dim3(block), lds, st, descs,
                                    items, brec, brec_u, stride, nitems, nrhs);
                 return hipGetLastError();
@@ -221,16 +224,14 @@ int batch_occupancy(csrk_dtype store, int nrhs, Shape s, bool adj, bool ind, boo
         using VT = decltype(vt);
         constexpr int VX = decltype(vc)::value, LL = decltype(lc)::value;
         if (adj) {
-            const size_t lds = size_t(s.waves) * kBatchLds;
-            return by_adj_variant(ind, adj_path(store, nrhs, all_sym, both), [&](auto ic, auto pc) -> hipError_t {
+            return by_adj_variant(ind, adj_path(nrhs, all_sym, both), [&](auto ic, auto pc) -> hipError_t {
                 constexpr bool IND = decltype(ic)::value;
                 constexpr int PATH = decltype(pc)::value;
                 if constexpr (!adj_variant_exists<VT, VX, PATH>())
                     return hipErrorInvalidValue;
                 else
-                    return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks,
-                                                                        k_batch_adjoint<VT, LL, VX, IND, PATH>, block,
-                                                                        lds);
+                    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                        &blocks, k_batch_adjoint<VT, LL, VX, IND, PATH>, block, size_t(s.waves) * adj_lds<VT, PATH>());
             });
         }
         return hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_batch_forward<VT, LL, VX>, block,

@@ -665,6 +665,14 @@ __device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__
 // (value, column) pairs, or (value, column, grad_vals) triples of 4-byte
 // values in the fused adjoint; sized for the largest.
 constexpr int kMrhsLds = kStageEntries * (8 + 4);
+// LDS bytes per wavefront of a multi-column adjoint: the fused window's
+// values, columns and grad_vals (FP64 accumulation stages 8-byte values), and
+// at least what the other multi-column layouts take.
+template <typename VT>
+__host__ __device__ constexpr int mrhs_adjoint_lds() {
+    constexpr int f = kStageEntries * int(2 * sizeof(typename Store<VT>::A) + sizeof(int32_t));
+    return f > kMrhsLds ? f : kMrhsLds;
+}
 // The multi-column forward needs only its own storage type's pairs.
 template <typename VT>
 __host__ __device__ constexpr int mrhs_forward_lds() {
@@ -1659,7 +1667,6 @@ __device__ __forceinline__ void mrhs_adjoint_fused_window(int32_t ra, int nrows,
                                                           int nrhs, unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
     constexpr int V = Store<VT>::V;
     constexpr int CAP = kStageEntries;
     constexpr int U = CAP / (kWave * V);
@@ -1778,7 +1785,7 @@ __device__ __forceinline__ void mrhs_adjoint_fused_window(int32_t ra, int nrows,
 // per row, VX columns each, gather the x and g slices of every entry j of
 // row i, add a_ji g_j into grad_x[i] and sum g_i . x_j over the columns into
 // grad_vals (LDS, then 16-byte stores).  LDS per wavefront: values, columns
-// and grad_vals of a window, 4 bytes each (FP32 accumulation only).
+// and grad_vals of a window (mrhs_adjoint_lds).
 template <typename VT, int RL, int VX, bool IND>
 __device__ __forceinline__ void sr_adjoint_fused_mrhs(int32_t r0, int32_t r1, const int32_t *__restrict__ row_ptr,
                                                       const int32_t *__restrict__ cols,
@@ -1790,7 +1797,6 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs(int32_t r0, int32_t r1, co
                                                       unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
     constexpr int V = Store<VT>::V;
     constexpr int WIN = kStageEntries - V;
     constexpr int RPP = kWave / RL;
@@ -2061,12 +2067,9 @@ __device__ __forceinline__ void sr_adjoint_mrhs(int32_t r0, int32_t r1, const in
                                                 typename Store<VT>::X *__restrict__ gx,
                                                 typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
                                                 bool sym, unsigned char *__restrict__ lds, int lane) {
-    if constexpr (sizeof(typename Store<VT>::A) == 4) {
-        if (sym && gx && gv) {
-            sr_adjoint_fused_mrhs<VT, RL, VX, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, nrhs, lds,
-                                                   lane);
-            return;
-        }
+    if (sym && gx && gv) {
+        sr_adjoint_fused_mrhs<VT, RL, VX, IND>(r0, r1, row_ptr, cols, t_src, valsT, x, g, gx, gv, nnz, nrhs, lds, lane);
+        return;
     }
     if (gv) sr_grad_vals_mrhs<VT, RL, VX>(r0, r1, row_ptr, cols, x, g, gv, nnz, nrhs, lds, lane);
     if (gx) sr_forward_mrhs<VT, RL, VX, IND>(r0, r1, t_row_ptr, t_col, t_src, valsT, g, gx, nnz, nrhs, lds, lane);

@@ -368,11 +368,9 @@ def test_adjoint_deterministic():
     assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
-@pytest.mark.parametrize("nrhs", [3, 8])
-@pytest.mark.parametrize("symmetric", [False, True])
-def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
+def _long_rows(rng, symmetric):
+    """n = 2500 rows of 1..7 entries, every 97th row with 1500 (past one LDS window); optionally symmetrised."""
     from gen import CsrInput
-    rng = np.random.default_rng(nrhs + 10 * symmetric)
     n = 2500
     dense_rows = set(range(0, n, 97))
     ii, jj = [], []
@@ -388,8 +386,16 @@ def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
     ii, jj = key // n, key % n
     rp = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(ii, minlength=n), out=rp[1:])
-    A = CsrInput("longsym" if symmetric else "long", n, rp.astype(np.int32), jj.astype(np.int32),
-                 rng.uniform(-1, 1, len(jj)).astype(np.float32).astype(np.float64), {})
+    return CsrInput("longsym" if symmetric else "long", n, rp.astype(np.int32), jj.astype(np.int32),
+                    rng.uniform(-1, 1, len(jj)).astype(np.float32).astype(np.float64), {})
+
+
+@pytest.mark.parametrize("nrhs", [3, 8])
+@pytest.mark.parametrize("symmetric", [False, True])
+def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
+    rng = np.random.default_rng(nrhs + 10 * symmetric)
+    A = _long_rows(rng, symmetric)
+    n = A.n
     X = rng.uniform(-1, 1, (n, nrhs)).astype(np.float32).astype(np.float64)
     G = rng.uniform(-1, 1, (n, nrhs)).astype(np.float32).astype(np.float64)
     say("adjoint mrhs long", nrhs, symmetric)
@@ -399,6 +405,24 @@ def test_adjoint_multi_rhs_long_rows(nrhs, symmetric):
     ref = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
     scale = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
     assert np.all(np.abs(gv - ref) <= OP.gamma(nrhs, 2.0 ** -24) * scale)
+
+
+@pytest.mark.parametrize("nrhs", [2, 8])
+@pytest.mark.parametrize("long_rows", [False, True])
+def test_adjoint_multi_rhs_symmetric_f64(nrhs, long_rows):
+    """FP64 storage, several right-hand sides, symmetric pattern: the one-pass multi-column adjoint (8-byte
+    values staged per window; rows past one window take the row-slice walk) against the oracle."""
+    rng = np.random.default_rng(90 + nrhs + long_rows)
+    A = _long_rows(rng, True) if long_rows else random_sparse(4000, 9.0, seed=91 + nrhs, empty_row_frac=0.05,
+                                                              symmetric_pattern=True)
+    X, G = rng.uniform(-1, 1, (A.n, nrhs)), rng.uniform(-1, 1, (A.n, nrhs))
+    say("adjoint mrhs symmetric f64", nrhs, long_rows)
+    M = _build(A, "f64", C.csrk_tune_rhs(A.n, A.nnz, nrhs, "mi355x"))
+    gx, gv = _adjoint(M, X, G)
+    _check_grad_x(gx, A, G, "f64", False, f"mrhs f64 {nrhs} {long_rows}")
+    ref = OA.grad_vals(A.row_ptr, A.col_idx, X, G)
+    scale = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(X), np.abs(G))
+    assert np.all(np.abs(gv - ref) <= 1e-12 * scale)
 
 
 def test_symmetric_values_share_the_forward_array():

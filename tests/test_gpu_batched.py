@@ -164,12 +164,14 @@ def test_c5_full_batch_adjoint_sampled_parity(full_c5):
 @pytest.mark.parametrize("store", ["f64", "f32", "bf16"])
 @pytest.mark.parametrize("nrhs", [1, 8])
 @pytest.mark.parametrize("explicit_vals", [False, True])
-def test_batch_adjoint_precisions_mixed_patterns(store, nrhs, explicit_vals):
-    """A batch mixing symmetric and nonsymmetric patterns in every storage type, one and eight right-hand sides,
-    handle values or values passed in: each matrix against the oracle at its bound and against its own
-    single-matrix launch."""
+@pytest.mark.parametrize("patterns", ["mixed", "symmetric"])
+def test_batch_adjoint_precisions_mixed_patterns(store, nrhs, explicit_vals, patterns):
+    """A batch mixing symmetric and nonsymmetric patterns (or of symmetric patterns only, which takes the
+    one-pass multi-column launch) in every storage type, one and eight right-hand sides, handle values or
+    values passed in: each matrix against the oracle at its bound and against its own single-matrix launch."""
     from gen import random_sparse
-    mats = [random_sparse(n, 6.0, seed=60 + i, empty_row_frac=0.05, symmetric_pattern=(i % 2 == 0))
+    mats = [random_sparse(n, 6.0, seed=60 + i, empty_row_frac=0.05,
+                          symmetric_pattern=(patterns == "symmetric" or i % 2 == 0))
             for i, n in enumerate((700, 1500, 90, 2300, 411))]
     rng = np.random.default_rng(61)
     for A in mats:
@@ -189,7 +191,7 @@ def test_batch_adjoint_precisions_mixed_patterns(store, nrhs, explicit_vals):
     xs = [to_dev(X[M.structure()["perm"]], dt) for X, M in zip(Xs, Ms)]
     gs = [to_dev(G[M.structure()["perm"]], dt) for G, M in zip(Gs, Ms)]
     vals = [M.values() for M in Ms] if explicit_vals else None
-    say("batch adjoint", store, nrhs, explicit_vals)
+    say("batch adjoint", store, nrhs, explicit_vals, patterns)
     gxs, gvs = B.adjoint(xs, gs, vals=vals)
     torch.cuda.synchronize()
     for i, (A, M) in enumerate(zip(mats, Ms)):
