@@ -665,12 +665,20 @@ __device__ __forceinline__ void long_row_adjoint(int32_t item, const int32_t *__
 // (value, column) pairs, or (value, column, grad_vals) triples of 4-byte
 // values in the fused adjoint; sized for the largest.
 constexpr int kMrhsLds = kStageEntries * (8 + 4);
+// Entries per window of the fused multi-column adjoint: half a window for
+// 8-byte values, so that its values, columns and grad_vals take no more LDS
+// than the FP32 window (more resident wavefronts).
+template <typename A>
+__host__ __device__ constexpr int mrhs_fused_cap() {
+    return sizeof(A) == 8 ? kStageEntries / 2 : kStageEntries;
+}
 // LDS bytes per wavefront of a multi-column adjoint: the fused window's
-// values, columns and grad_vals (FP64 accumulation stages 8-byte values), and
-// at least what the other multi-column layouts take.
+// values, columns and grad_vals, and at least what the other multi-column
+// layouts take.
 template <typename VT>
 __host__ __device__ constexpr int mrhs_adjoint_lds() {
-    constexpr int f = kStageEntries * int(2 * sizeof(typename Store<VT>::A) + sizeof(int32_t));
+    using A = typename Store<VT>::A;
+    constexpr int f = mrhs_fused_cap<A>() * int(2 * sizeof(A) + sizeof(int32_t));
     return f > kMrhsLds ? f : kMrhsLds;
 }
 // The multi-column forward needs only its own storage type's pairs.
@@ -1668,7 +1676,7 @@ __device__ __forceinline__ void mrhs_adjoint_fused_window(int32_t ra, int nrows,
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
-    constexpr int CAP = kStageEntries;
+    constexpr int CAP = mrhs_fused_cap<A>();
     constexpr int U = CAP / (kWave * V);
     constexpr int RPP = kWave / RL;
     constexpr int CPP = RL * VX;
@@ -1798,7 +1806,7 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs(int32_t r0, int32_t r1, co
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
     constexpr int V = Store<VT>::V;
-    constexpr int WIN = kStageEntries - V;
+    constexpr int WIN = mrhs_fused_cap<A>() - V;
     constexpr int RPP = kWave / RL;
     constexpr int CPP = RL * VX;
     const int q = lane % RL;
@@ -1877,7 +1885,7 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs_rec(const SrRec &rec, cons
                                                           typename Store<VT>::X *__restrict__ gx,
                                                           typename Store<VT>::A *__restrict__ gv, int64_t nnz, int nrhs,
                                                           unsigned char *__restrict__ lds, int lane) {
-    constexpr int WIN = kStageEntries - Store<VT>::V;
+    constexpr int WIN = mrhs_fused_cap<typename Store<VT>::A>() - Store<VT>::V;
     const int nrows = rec.r1 - rec.r0;
     if (nrows > kWave || rec.e1 - rec.e0 > WIN) {
         sr_adjoint_fused_mrhs<VT, RL, VX, IND>(rec.r0, rec.r1, row_ptr, cols, src, valsT, x, g, gx, gv, nnz, nrhs, lds,
