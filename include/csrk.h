@@ -118,9 +118,9 @@ typedef struct csrk_info {
     csrk_params params;
     int32_t adjoint_union;    /* 1 when uploaded with a nonsymmetric pattern whose union
                                  pattern (A' + A'^T) fits the staging windows: the
-                                 single-right-hand-side adjoint then takes both gradients
-                                 in one pass over the union instead of a pass over A' and
-                                 one over A'^T */
+                                 adjoint (one or several right-hand sides) then takes both
+                                 gradients in one pass over the union instead of a pass
+                                 over A' and one over A'^T */
 } csrk_info;
 
 typedef struct csrk_matrix *csrk_handle;

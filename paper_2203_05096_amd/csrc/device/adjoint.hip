@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
     const int lane = threadIdx.x & (kWave - 1);
     const int wave = uniform(threadIdx.x / kWave);
     const int nw = blockDim.x / kWave;
-    unsigned char *lds = smem + size_t(wave) * mrhs_adjoint_lds<VT>();
+    unsigned char *lds = smem + size_t(wave) * (srec_u ? union_mrhs_lds<VT>() : mrhs_adjoint_lds<VT>());
     const int32_t t = ssr_of_block(split, int32_t(blockIdx.x));
     if (t < 0) return;
     for (int32_t w = wave; w < stride; w += nw) {
@@ -94,13 +94,10 @@ __global__ void __launch_bounds__(1024) k_adjoint_csrk_mrhs(
                                                        lane);
             continue;
         }
-        if constexpr (sizeof(typename Store<VT>::A) == 4) {
-            if (srec_u && gx && gv) {  // nonsymmetric: one pass over the union pattern
-                mrhs_adjoint_union_window<VT, RL, VX, IND>(rec, srec_u[int64_t(t) * stride + w], row_ptr, erow_ptr,
-                                                           u_col, u_src, IND ? valsT : u_vals, x, g, gx, gv, nu,
-                                                           nrhs, lds, lane);
-                continue;
-            }
+        if (srec_u && gx && gv) {  // nonsymmetric: one pass over the union pattern
+            mrhs_adjoint_union_window<VT, RL, VX, IND>(rec, srec_u[int64_t(t) * stride + w], row_ptr, erow_ptr, u_col,
+                                                       u_src, IND ? valsT : u_vals, x, g, gx, gv, nu, nrhs, lds, lane);
+            continue;
         }
         sr_adjoint_mrhs<VT, RL, VX, IND>(rec.r0, rec.r1, row_ptr, cols, t_row_ptr, t_col, t_src, valsT, x, g, gx, gv,
                                          nnz, nrhs, sym != 0, lds, lane);
@@ -163,6 +160,8 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                 });
             }
             const VT *vsrc = static_cast<const VT *>(ind ? vals : a.vals_t);
+            const SrRec *srec_u = a.sym ? nullptr : a.srec_u;
+            const size_t lds = size_t(s.waves) * (srec_u ? union_mrhs_lds<VT>() : mrhs_adjoint_lds<VT>());
             const int vx = vec_cols<X>(nrhs, {x, g, gx});
             return by_vx<X>(vx, [&](auto vc) -> hipError_t {
                 constexpr int VX = decltype(vc)::value;
@@ -170,11 +169,10 @@ hipError_t adjoint(const Arrays &a, csrk_dtype store, const void *vals, const vo
                     constexpr int RL = decltype(rc)::value;
                     // with caller values the union pass reaches them through u_src (valsT is then the caller's)
                     hipLaunchKernelGGL((k_adjoint_csrk_mrhs<VT, RL, VX, IND>), dim3(a.split_adj.width * kXcds),
-                                       dim3(block), size_t(s.waves) * mrhs_adjoint_lds<VT>(), st, a.srec,
-                                       a.srec_stride, a.row_ptr, a.col_idx, a.t_row_ptr, a.t_col, a.t_src, vsrc,
-                                       static_cast<const X *>(x), static_cast<const X *>(g), static_cast<X *>(gx),
-                                       static_cast<A *>(gv), a.nnz, nrhs, int(a.sym), a.split_adj,
-                                       a.sym ? nullptr : a.srec_u, a.erow_ptr, a.u_col, a.u_src,
+                                       dim3(block), lds, st, a.srec, a.srec_stride, a.row_ptr, a.col_idx,
+                                       a.t_row_ptr, a.t_col, a.t_src, vsrc, static_cast<const X *>(x),
+                                       static_cast<const X *>(g), static_cast<X *>(gx), static_cast<A *>(gv), a.nnz,
+                                       nrhs, int(a.sym), a.split_adj, srec_u, a.erow_ptr, a.u_col, a.u_src,
                                        static_cast<const VT *>(a.u_vals), a.nu);
                     return hipGetLastError();
                 });

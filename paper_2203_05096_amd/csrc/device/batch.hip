@@ -55,10 +55,11 @@ __global__ void __launch_bounds__(1024) k_batch_forward(const MatDesc *__restric
 // two-phase per matrix).
 enum BatchAdjPath { kAdjSingle = 0, kAdjMrhsFused = 1, kAdjMrhsAny = 2 };
 
-// LDS bytes per wavefront of a batched adjoint path.
+// LDS bytes per wavefront of a batched adjoint path (the general
+// multi-column path may take the union window).
 template <typename VT, int PATH>
 __host__ __device__ constexpr int adj_lds() {
-    return PATH == kAdjSingle ? kBatchLds : mrhs_adjoint_lds<VT>();
+    return PATH == kAdjSingle ? kBatchLds : PATH == kAdjMrhsFused ? mrhs_adjoint_lds<VT>() : union_mrhs_lds<VT>();
 }
 
 template <typename VT, int L, int VX, bool IND, int PATH>
@@ -110,15 +111,12 @@ __global__ void __launch_bounds__(1024) k_batch_adjoint(const MatDesc *__restric
                 sr_adjoint_fused_mrhs_rec<VT, L, VX, IND>(rec, row_ptr, col_idx, t_src, vals, x, g, gx, gv, d.nnz,
                                                           nrhs, lds, lane);
             } else {
-                if constexpr (sizeof(A) == 4) {
-                    if (uni) {
-                        mrhs_adjoint_union_window<VT, L, VX, IND>(
-                            rec, brec_u[int64_t(it) * stride + w], row_ptr, global_ptr(d.erow_ptr),
-                            global_ptr(d.u_col), global_ptr(d.u_src),
-                            IND ? vals : global_ptr(static_cast<const VT *>(d.u_vals)), x, g, gx, gv, d.nu, nrhs, lds,
-                            lane);
-                        continue;
-                    }
+                if (uni) {
+                    mrhs_adjoint_union_window<VT, L, VX, IND>(
+                        rec, brec_u[int64_t(it) * stride + w], row_ptr, global_ptr(d.erow_ptr), global_ptr(d.u_col),
+                        global_ptr(d.u_src), IND ? vals : global_ptr(static_cast<const VT *>(d.u_vals)), x, g, gx, gv,
+                        d.nu, nrhs, lds, lane);
+                    continue;
                 }
                 sr_adjoint_mrhs<VT, L, VX, IND>(r0, r1, row_ptr, col_idx, t_row_ptr, t_col, t_src, vals, x, g, gx, gv,
                                                 d.nnz, nrhs, d.sym != 0, lds, lane);

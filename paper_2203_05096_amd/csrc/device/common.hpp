@@ -681,6 +681,13 @@ __host__ __device__ constexpr int mrhs_adjoint_lds() {
     constexpr int f = mrhs_fused_cap<A>() * int(2 * sizeof(A) + sizeof(int32_t));
     return f > kMrhsLds ? f : kMrhsLds;
 }
+// LDS bytes per wavefront of a multi-column adjoint that may take the union
+// window (values, columns and grad_vals of a full window).
+template <typename VT>
+__host__ __device__ constexpr int union_mrhs_lds() {
+    constexpr int f = kStageEntries * int(2 * sizeof(typename Store<VT>::A) + sizeof(int32_t));
+    return f > mrhs_adjoint_lds<VT>() ? f : mrhs_adjoint_lds<VT>();
+}
 // The multi-column forward needs only its own storage type's pairs.
 template <typename VT>
 __host__ __device__ constexpr int mrhs_forward_lds() {
@@ -1904,7 +1911,7 @@ __device__ __forceinline__ void sr_adjoint_fused_mrhs_rec(const SrRec &rec, cons
 // (grad_vals[k] = sum_c g_ic x_jc, grad_x[i] += a'_ji g_j), then its extras,
 // gathering g only.  `ra` / `ru`: the super-row's records in A' and in U; the
 // host builds U only when every super-row has at most 64 rows and fits one
-// window.  FP32 accumulation only.
+// window.  LDS per wavefront: union_mrhs_lds.
 template <typename VT, int RL, int VX, bool IND>
 __device__ __forceinline__ void mrhs_adjoint_union_window(const SrRec &ra, const SrRec &ru,
                                                           const int32_t *__restrict__ row_ptr,
@@ -1918,7 +1925,6 @@ __device__ __forceinline__ void mrhs_adjoint_union_window(const SrRec &ra, const
                                                           int nrhs, unsigned char *__restrict__ lds, int lane) {
     using A = typename Store<VT>::A;
     using X = typename Store<VT>::X;
-    static_assert(sizeof(A) == 4, "the fused multi-column adjoint stages 4-byte values");
     constexpr int V = Store<VT>::V;
     constexpr int CAP = kStageEntries;
     constexpr int U = CAP / (kWave * V);

@@ -223,27 +223,33 @@ def test_batch_adjoint_precisions_mixed_patterns(store, nrhs, explicit_vals, pat
 
 @pytest.mark.parametrize("nrhs", [1, 4])
 @pytest.mark.parametrize("explicit_vals", [False, True])
-def test_batch_adjoint_union(nrhs, explicit_vals):
-    """A batch of nonsymmetric matrices that all have a union-pattern index: the batched adjoint takes one pass
-    over each union (values from the handles' union copies or passed in) and matches the oracle."""
+@pytest.mark.parametrize("store", ["f32", "f64"])
+def test_batch_adjoint_union(nrhs, explicit_vals, store):
+    """A batch of nonsymmetric matrices that all have a union-pattern index, FP32 and FP64 storage: the batched
+    adjoint takes one pass over each union (values from the handles' union copies or passed in) and matches the
+    oracle."""
     from gen import random_sparse
     mats = [random_sparse(n, 5.0, seed=80 + i, empty_row_frac=0.05) for i, n in enumerate((900, 1700, 333))]
     for A in mats:
-        A.vals = OP.stored_values(A.vals, "f32")
+        A.vals = OP.stored_values(A.vals, store)
     p = {"k": 3, "srs": 16, "ssrs": 2, "lanes_per_row": 2, "waves_per_wg": 2, "reorder": "bandk"}
-    Ms = [CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, "f32"), "f32") for A in mats]
+    Ms = [CsrkMatrix(C.csrk_build(A.row_ptr, A.col_idx, A.vals, p, store), store) for A in mats]
     assert all(M.info["adjoint_union"] == 1 for M in Ms)
     B = CsrkBatch(Ms)
     rng = np.random.default_rng(81)
+    dt = torch.float64 if store == "f64" else torch.float32
     Xs, Gs = [], []
     for A in mats:
         shp = (A.n,) if nrhs == 1 else (A.n, nrhs)
-        Xs.append(rng.uniform(-1, 1, shp).astype(np.float32).astype(np.float64))
-        Gs.append(rng.uniform(-1, 1, shp).astype(np.float32).astype(np.float64))
-    xs = [to_dev(X[M.structure()["perm"]], torch.float32) for X, M in zip(Xs, Ms)]
-    gs = [to_dev(G[M.structure()["perm"]], torch.float32) for G, M in zip(Gs, Ms)]
+        X, G = rng.uniform(-1, 1, shp), rng.uniform(-1, 1, shp)
+        if store != "f64":
+            X, G = X.astype(np.float32).astype(np.float64), G.astype(np.float32).astype(np.float64)
+        Xs.append(X)
+        Gs.append(G)
+    xs = [to_dev(X[M.structure()["perm"]], dt) for X, M in zip(Xs, Ms)]
+    gs = [to_dev(G[M.structure()["perm"]], dt) for G, M in zip(Gs, Ms)]
     vals = [M.values() for M in Ms] if explicit_vals else None
-    say("batch adjoint union", nrhs, explicit_vals)
+    say("batch adjoint union", store, nrhs, explicit_vals)
     gxs, gvs = B.adjoint(xs, gs, vals=vals)
     torch.cuda.synchronize()
     for i, (A, M) in enumerate(zip(mats, Ms)):
@@ -256,12 +262,16 @@ def test_batch_adjoint_union(nrhs, explicit_vals):
         scale = OA.grad_x(A.row_ptr, A.col_idx, np.abs(A.vals), np.abs(Gs[i]))
         cc = np.maximum(np.bincount(A.col_idx, minlength=A.n), 1)
         cc = cc if nrhs == 1 else cc[:, None]
-        assert np.all(np.abs(gx_in - ref) <= OP.gamma(cc, 2.0 ** -24) * scale), i
+        beta = 1e-12 if store == "f64" else OP.gamma(cc, 2.0 ** -24)
+        assert np.all(np.abs(gx_in - ref) <= beta * scale), i
         refv = OA.grad_vals(A.row_ptr, A.col_idx, Xs[i], Gs[i])
         if nrhs == 1:
-            assert np.array_equal(gv_in, refv.astype(np.float32).astype(np.float64)), i
+            # one rounded product per entry: bitwise in either precision
+            refv = refv if store == "f64" else refv.astype(np.float32).astype(np.float64)
+            assert np.array_equal(gv_in, refv), i
         else:
             scalev = OA.grad_vals(A.row_ptr, A.col_idx, np.abs(Xs[i]), np.abs(Gs[i]))
-            assert np.all(np.abs(gv_in - refv) <= OP.gamma(nrhs, 2.0 ** -24) * scalev), i
+            betav = 1e-12 if store == "f64" else OP.gamma(nrhs, 2.0 ** -24)
+            assert np.all(np.abs(gv_in - refv) <= betav * scalev), i
     B.close()
 
